@@ -359,6 +359,8 @@ struct ref_ctx {
   /* particles */
   int np, capp;
   double *X, *U, *Om, *D, *rho, *M, *V, *I, *Fh, *Th, *Fc, *cbuoy;
+  double *Pin, *Lin, *Pprev, *Lprev; /* fluid momentum inside each particle: now, last step */
+  double *Hprev, *Gprev; /* hydrodynamic force and torque of the previous step */
   int *mstart, *mcount;
   /* markers */
   int nmk, capm;
@@ -410,7 +412,7 @@ ref_ctx* ref_create(const ref_config* cfg) {
 
 static void free_particles(ref_ctx* c) {
   double** arrs[] = {&c->X, &c->U, &c->Om, &c->D, &c->rho, &c->M, &c->V, &c->I,
-                     &c->Fh, &c->Th, &c->Fc, &c->cbuoy};
+                     &c->Fh, &c->Th, &c->Fc, &c->cbuoy, &c->Pin, &c->Lin, &c->Pprev, &c->Lprev, &c->Hprev, &c->Gprev};
   for (size_t i = 0; i < sizeof(arrs) / sizeof(arrs[0]); i++) free(*arrs[i]);
   free(c->mstart);
   free(c->mcount);
@@ -457,6 +459,8 @@ int32_t ref_get_pdfs(const ref_ctx* c, double* f) {
 }
 
 /* ---- particles ---------------------------------------------------------- */
+
+static void interior_momentum(ref_ctx* c, const double* uvel, double* P, double* L);
 
 /* Lagrangian points on the particle surface (the paper places them uniformly):
  * 2-D, equal angles on the circle; 3-D, the Fibonacci (golden-angle) sphere. */
@@ -556,6 +560,12 @@ int32_t ref_add_particles(ref_ctx* c, int32_t n, const double* center, const dou
   GROW(c->Fh, double, 3 * np);
   GROW(c->Th, double, 3 * np);
   GROW(c->Fc, double, 3 * np);
+  GROW(c->Pin, double, 3 * np);
+  GROW(c->Lin, double, 3 * np);
+  GROW(c->Pprev, double, 3 * np);
+  GROW(c->Lprev, double, 3 * np);
+  GROW(c->Hprev, double, 3 * np);
+  GROW(c->Gprev, double, 3 * np);
   GROW(c->D, double, np);
   GROW(c->rho, double, np);
   GROW(c->M, double, np);
@@ -576,6 +586,7 @@ int32_t ref_add_particles(ref_ctx* c, int32_t n, const double* center, const dou
       c->U[3 * p + a] = velocity ? velocity[3 * i + a] : 0.0;
       c->Om[3 * p + a] = omega ? omega[3 * i + a] : 0.0;
       c->Fh[3 * p + a] = c->Th[3 * p + a] = c->Fc[3 * p + a] = 0.0;
+      c->Hprev[3 * p + a] = c->Gprev[3 * p + a] = 0.0;
     }
     if (dim == 2) {
       c->X[3 * p + 2] = c->U[3 * p + 2] = 0.0;
@@ -618,10 +629,28 @@ int32_t ref_add_particles(ref_ctx* c, int32_t n, const double* center, const dou
       for (int a = 0; a < 3; a++) c->mF[3 * m + a] = c->mFprev[3 * m + a] = 0.0;
     }
   }
+  int np_old = c->np;
   c->np = np;
   c->nmk = nmk;
   cells_setup(c);
   find_pairs(c);
+  /* interior fluid momentum of the new particles in the current fluid */
+  {
+    long N = c->N;
+    for (long i = 0; i < N; i++) {
+      double fl[19], pp, uu[3];
+      fl[0] = 0.0;
+      for (int a = 1; a < c->q; a++) fl[a] = c->f[(a - 1) * N + i];
+      ref_macro(dim, c->cfg.rho0, fl, &pp, uu);
+      for (int a = 0; a < dim; a++) c->g[a * N + i] = uu[a];
+    }
+    interior_momentum(c, c->g, c->Pin, c->Lin);
+    for (int p = np_old; p < np; p++)
+      for (int a = 0; a < 3; a++) {
+        c->Pprev[3 * p + a] = c->Pin[3 * p + a];
+        c->Lprev[3 * p + a] = c->Lin[3 * p + a];
+      }
+  }
   return 0;
 }
 
@@ -905,22 +934,86 @@ static void pair_forces(ref_ctx* c) {
     }
 }
 
+/* Momentum and angular momentum of the fluid inside each particle,
+ *   P = sum_x chi(x) rho0 u(x),  L = sum_x chi(x) (x - X_c) x rho0 u(x),
+ * with u a velocity field (d x N) and chi a volume indicator that falls
+ * linearly from 1 to 0 across one lattice spacing at the surface:
+ * chi = clamp(R + 1/2 - |x - X_c|, 0, 1).  Nodes in x-outer, y, z-inner order. */
+static void interior_momentum(ref_ctx* c, const double* uvel, double* P, double* L) {
+  const ref_config* k = &c->cfg;
+  long N = c->N;
+  for (int p = 0; p < c->np; p++) {
+    const double* Xc = c->X + 3 * p;
+    double R = 0.5 * c->D[p];
+    double Pa[3] = {0, 0, 0}, La[3] = {0, 0, 0};
+    long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < c->dim; a++) {
+      lo[a] = (long)floor(Xc[a] - R - 0.5);
+      hi[a] = (long)ceil(Xc[a] + R + 0.5);
+      if (lo[a] < 0) lo[a] = 0;
+      if (hi[a] > k->n[a] - 1) hi[a] = k->n[a] - 1;
+    }
+    for (long i = lo[0]; i <= hi[0]; i++)
+      for (long j = lo[1]; j <= hi[1]; j++)
+        for (long l = lo[2]; l <= hi[2]; l++) {
+          double r[3] = {(double)i - Xc[0], (double)j - Xc[1], c->dim == 3 ? (double)l - Xc[2] : 0.0};
+          double d2 = 0.0;
+          for (int a = 0; a < c->dim; a++) d2 = d2 + r[a] * r[a];
+          double chi = R + 0.5 - sqrt(d2);
+          if (chi <= 0.0) continue;
+          if (chi > 1.0) chi = 1.0;
+          long node = i + k->n[0] * (j + (long)k->n[1] * l);
+          double m[3] = {0, 0, 0};
+          for (int a = 0; a < c->dim; a++) m[a] = chi * (k->rho0 * uvel[a * N + node]);
+          double t[3] = {r[1] * m[2] - r[2] * m[1], r[2] * m[0] - r[0] * m[2],
+                         r[0] * m[1] - r[1] * m[0]};
+          for (int a = 0; a < 3; a++) {
+            Pa[a] = Pa[a] + m[a];
+            La[a] = La[a] + t[a];
+          }
+        }
+    for (int a = 0; a < 3; a++) {
+      P[3 * p + a] = Pa[a];
+      L[3 * p + a] = La[a];
+    }
+  }
+}
+
 static void newton_euler(ref_ctx* c) {
-  /* Eqs. 14-15 with the interior fluid moving rigidly: effective mass M - rho0 V,
-   * buoyant weight (M - rho0 V) g, effective inertia I (1 - rho0/rho_p); explicit
-   * Euler for the velocities and the trapezoid rule for the position. */
+  /* Eqs. 14-15.  F_b is the buoyant weight (M - rho0 V) g.  F_f and T_f, which keep the
+   * fluid inside the particle moving with it, are the rates of change of the momentum
+   * and angular momentum of the fluid inside the moving particle volume, taken after
+   * streaming at consecutive steps: P^n - P^(n-1), L^n - L^(n-1) (dt = 1).  When that
+   * fluid moves rigidly, P = rho0 V U and Eq. 14 becomes
+   * (M - rho0 V) dU/dt = F_h + F_c + (M - rho0 V) g.
+   * The hydrodynamic load H = F_h + F_f (and G = T_h + T_f) is averaged over the current
+   * and the previous step: the split forcing of Eqs. 7-8 answers a force with an
+   * overshoot one step later, and the two-step average removes the alternating mode
+   * that this feeds when the particle is light.  Explicit Euler for the velocities and
+   * the trapezoid rule for the position. */
   const ref_config* k = &c->cfg;
   for (int p = 0; p < c->np; p++) {
     double meff = c->M[p] - k->rho0 * c->V[p];
-    double ieff = c->I[p] * (1.0 - k->rho0 / c->rho[p]);
     for (int a = 0; a < c->dim; a++) {
       double U0 = c->U[3 * p + a];
-      double U1 = U0 + (c->Fh[3 * p + a] + c->Fc[3 * p + a] + meff * k->gravity[a]) / meff;
+      double H = c->Fh[3 * p + a] + (c->Pin[3 * p + a] - c->Pprev[3 * p + a]);
+      double Havg = 0.5 * (H + c->Hprev[3 * p + a]);
+      double U1 = U0 + (Havg + c->Fc[3 * p + a] + meff * k->gravity[a]) / c->M[p];
+      c->Hprev[3 * p + a] = H;
       c->U[3 * p + a] = U1;
       c->X[3 * p + a] = c->X[3 * p + a] + 0.5 * (U0 + U1);
     }
     int a0 = c->dim == 2 ? 2 : 0;
-    for (int a = a0; a < 3; a++) c->Om[3 * p + a] = c->Om[3 * p + a] + c->Th[3 * p + a] / ieff;
+    for (int a = a0; a < 3; a++) {
+      double G = c->Th[3 * p + a] + (c->Lin[3 * p + a] - c->Lprev[3 * p + a]);
+      double Gavg = 0.5 * (G + c->Gprev[3 * p + a]);
+      c->Gprev[3 * p + a] = G;
+      c->Om[3 * p + a] = c->Om[3 * p + a] + Gavg / c->I[p];
+    }
+    for (int a = 0; a < 3; a++) {
+      c->Pprev[3 * p + a] = c->Pin[3 * p + a];
+      c->Lprev[3 * p + a] = c->Lin[3 * p + a];
+    }
   }
 }
 
@@ -957,6 +1050,15 @@ int32_t ref_step(ref_ctx* c, int32_t nsteps) {
     }
     /* (5) particles */
     if (c->np > 0) {
+      /* momentum of the fluid inside each particle after streaming (u* of the new PDFs) */
+      for (long i = 0; i < N; i++) {
+        double fl[19], pp, uu[3];
+        fl[0] = 0.0;
+        for (int a = 1; a < q; a++) fl[a] = c->f[(a - 1) * N + i];
+        ref_macro(d, c->cfg.rho0, fl, &pp, uu);
+        for (int a = 0; a < d; a++) c->g[a * N + i] = uu[a];
+      }
+      interior_momentum(c, c->g, c->Pin, c->Lin);
       particle_loads(c);
       pair_forces(c);
       newton_euler(c);
