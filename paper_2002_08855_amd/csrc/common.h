@@ -1,0 +1,206 @@
+// Internal declarations of the gfx950 IB-LBM library: lattice tables, storage traits,
+// device-state layout and the launchers each translation unit provides.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/iblbm.h"
+
+// ---------------------------------------------------------------------------
+// Lattices.  D2Q9 follows Eq. 2 and D3Q19 Eq. 3 (third row completed so that
+// e_9 = (-1,0,1)); directions alpha > (q-1)/2 are the negatives of alpha-(q-1)/2.
+template <int DIM>
+struct Lat;
+template <>
+struct Lat<2> {
+  static constexpr int Q = 9, H = 4;
+  static constexpr int ex[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+  static constexpr int ey[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+  static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36,
+                                  1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
+};
+template <>
+struct Lat<3> {
+  static constexpr int Q = 19, H = 9;
+  static constexpr int ex[19] = {0, 1, 0, 0, 1, -1, 0, 0, 1, -1, -1, 0, 0, -1, 1, 0, 0, -1, 1};
+  static constexpr int ey[19] = {0, 0, 1, 0, 1, 1, 1, -1, 0, 0, 0, -1, 0, -1, -1, -1, 1, 0, 0};
+  static constexpr int ez[19] = {0, 0, 0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+__host__ __device__ constexpr int opp_dir(int a, int h) { return a <= h ? a + h : a - h; }
+
+// ---------------------------------------------------------------------------
+// PDF storage types.  The compute type is double for FP64 storage, float otherwise.
+struct bf16s {
+  uint16_t v;
+};
+template <class T>
+struct Store;
+template <>
+struct Store<double> {
+  using C = double;
+  __device__ static double load(double s, double) { return s; }
+  __device__ static double save(double f, double) { return f; }
+};
+template <>
+struct Store<float> {
+  using C = float;
+  __device__ static float load(float s, float) { return s; }
+  __device__ static float save(float f, float) { return f; }
+};
+template <>
+struct Store<bf16s> {
+  using C = float;
+  __device__ static float load(bf16s s, float) { return __uint_as_float(uint32_t(s.v) << 16); }
+  // round to nearest even; NaN stays NaN
+  __device__ static bf16s save(float f, float) {
+    uint32_t u = __float_as_uint(f);
+    bf16s r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      r.v = uint16_t((u >> 16) | 0x40u);
+      return r;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    r.v = uint16_t(u >> 16);
+    return r;
+  }
+};
+template <>
+struct Store<__half> {
+  using C = float;
+  // stored value = scale * f; load multiplies by 1/scale (exact for a power of two)
+  __device__ static float load(__half s, float inv_scale) { return __half2float(s) * inv_scale; }
+  __device__ static __half save(float f, float inv_scale) { return __float2half(f / inv_scale); }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry shared by the fluid kernels.
+template <class C>
+struct Geo {
+  int n[3];
+  int periodic[3];
+  long long N;
+  C rho0;
+  C wt[19][6];  // 2 w_a rho0 (e_a . u_wall[face]) / cs^2
+};
+
+// Segment flags: one 32-bit word per 16 consecutive x-nodes of a row.
+constexpr int SEG = 16;
+
+// ---------------------------------------------------------------------------
+// Host-side context.
+struct iblbm_ctx {
+  iblbm_config cfg;
+  int dim = 2, q = 9;
+  long long N = 0;
+  int storage = 0;
+  size_t sbytes = 8;  // bytes per stored PDF
+  bool fp64 = true;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::string err;
+  int sticky = 0;
+  long long step = 0;
+  int parity = 0;  // 0: natural layout; 1: A-A swapped layout
+  // fluid
+  void* f = nullptr;        // (q-1) x N, storage type
+  void* ustar = nullptr;    // band u*, N x VD compute type
+  void* facc = nullptr;     // IB force density, N x VD compute type
+  int vd = 2;               // vector stride of ustar / facc (2 in 2-D, 4 in 3-D)
+  uint32_t* bflag = nullptr;  // nseg flags
+  int* seglist = nullptr;     // flagged segments
+  int* segcount = nullptr;    // two counters used alternately (see ibm_clear_and_mark)
+  int segcur = 0;             // index of the counter that holds the current count
+  long long nseg = 0, nsegx = 0;
+  // particles (FP64)
+  int np = 0, capp = 0;
+  double *X = nullptr, *U = nullptr, *Om = nullptr, *Fh = nullptr, *Th = nullptr,
+         *Fc = nullptr, *Pin = nullptr, *Lin = nullptr, *Pprev = nullptr, *Lprev = nullptr,
+         *Hprev = nullptr, *Gprev = nullptr;
+  double *D = nullptr, *rho = nullptr, *M = nullptr, *V = nullptr, *I = nullptr,
+         *cb = nullptr;
+  int *mstart = nullptr, *mcount = nullptr;
+  std::vector<double> hD, hX;  // host copies used for validation
+  std::vector<int> hcount;
+  double dmax = 0.0;
+  int max_box = 0;  // max marker-stencil box side for LDS binning
+  // markers
+  int nmk = 0, capm = 0;
+  int* mown = nullptr;
+  double* mr = nullptr;     // nmk x 4 offsets r_k (FP64)
+  double* mdV = nullptr;    // nmk
+  void* mF = nullptr;       // accumulated force, nmk x 4 compute type
+  void* mdF = nullptr;      // pass increment, nmk x 4
+  void* mFprev = nullptr;   // previous-step force, nmk x 4
+  // cells and pairs
+  int nc[3] = {1, 1, 1};
+  double invh[3] = {0, 0, 0};
+  long long ncell = 0;
+  int* cell_count = nullptr;
+  int* cell_items = nullptr;  // ncell x CELL_CAP
+  int* cell_of = nullptr;     // np x 3
+  int* pair_up = nullptr;     // np x PAIR_CAP partners j > i, ascending
+  int* pair_nup = nullptr;    // np
+  // status and statistics
+  int* dstatus = nullptr;     // [0] flags, [1] truncated (int64 at [2..3]), ...
+  double* dstats = nullptr;   // [0] slip sum of squares
+  long long truncated = 0;
+  double slip_rms = 0.0;
+  int fallbacks = 0;
+  // learned forcing
+  bool has_mlp = false;
+  void* mlp_w = nullptr;      // packed weights for inference
+  float* mlp_norm = nullptr;  // 26 floats
+  float* feat = nullptr;      // nmk x 10 scratch
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_group;
+  size_t ev_used = 0;
+  double time_ms[IBLBM_NGROUPS] = {0};
+  long long launches[IBLBM_NGROUPS] = {0};
+  // graphs
+  bool use_graph = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool graph_dirty = true;
+  // allocations
+  std::vector<void*> allocs;
+};
+
+constexpr int CELL_CAP = 8;
+constexpr int PAIR_CAP = 24;
+constexpr int MAX_BOX_3D = 46;  // D <= 40 with a 4-point stencil
+
+// status bits
+constexpr int ST_CELL_OVERFLOW = 1, ST_PAIR_OVERFLOW = 2, ST_NAN = 4;
+
+// ---------------------------------------------------------------------------
+// Launchers (all enqueue on ctx->stream).
+void lbm_init_equilibrium(iblbm_ctx* c, const double* dp, const double* du);
+void lbm_set_pdfs(iblbm_ctx* c, const double* df);
+void lbm_get_pdfs(iblbm_ctx* c, double* df);
+void lbm_get_fields(iblbm_ctx* c, double* dp, double* du, double* dforce);
+void lbm_collide_stream(iblbm_ctx* c);
+void lbm_band_prep(iblbm_ctx* c);
+void ibm_clear_and_mark(iblbm_ctx* c);
+void ibm_interp(iblbm_ctx* c, int first_pass, int mode);
+void ibm_spread(iblbm_ctx* c, int use_set);
+void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L);
+void ibm_slip(iblbm_ctx* c);
+void part_cells_pairs(iblbm_ctx* c);
+void part_loads_newton(iblbm_ctx* c);
+void mlp_features(iblbm_ctx* c);
+void mlp_infer(iblbm_ctx* c);
+
+// timing helpers (host.hip)
+void tbegin(iblbm_ctx* c, int group);
+void tend(iblbm_ctx* c);

@@ -1,0 +1,591 @@
+// Fluid kernels for gfx950: the fused collide + Guo force + A-A in-place stream step,
+// the band u* pass of the immersed boundary, and state initialisation / gathers.
+//
+// Layout: SoA, slot a-1 holds direction a = 1..q-1 for all N nodes (f_0 is never
+// needed: it enters neither u* nor p, Sec. 3.1).  A-A pattern: after an even step the
+// post-collision value of direction a at node x sits in the opposite slot at x; an odd
+// step reads it from the neighbour x - e_a and pushes its own results to x + e_a, so
+// each thread reads and writes the same set of locations and the update is in place
+// and race free.  Links that leave through a wall bounce back half-way with the
+// moving-wall term 2 w_a rho0 (e_a . u_w)/c_s^2.
+#include "common.h"
+
+namespace {
+
+template <int DIM, class C>
+struct NodeCtx {
+  int x, y, z;
+  int i;
+};
+
+// Neighbour along +d (d = +-e_a) of node (x,y,z) and whether the link leaves through a
+// wall (then 'face' is the first wall face crossed, in axis order).
+template <int DX, int DY, int DZ, class C>
+__device__ __forceinline__ int neighbour(const Geo<C>& g, int x, int y, int z, bool& wall,
+                                         int& face) {
+  int c[3] = {x + DX, y + DY, z + DZ};
+  const int d[3] = {DX, DY, DZ};
+  wall = false;
+  face = 0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (d[a] == 0) continue;
+    bool lo = c[a] < 0, hi = c[a] >= g.n[a];
+    if (lo || hi) {
+      if (g.periodic[a]) {
+        c[a] = lo ? c[a] + g.n[a] : c[a] - g.n[a];
+      } else if (!wall) {
+        wall = true;
+        face = 2 * a + (hi ? 1 : 0);
+      }
+    }
+  }
+  return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+}
+
+template <int DIM, class T, int PAR, int A>
+struct LoadDir {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  __device__ __forceinline__ static C run(T* const* slot, const Geo<C>& g, int x, int y, int z,
+                                          int i, C inv_s) {
+    if (PAR == 0) return Store<T>::load(slot[A - 1][i], inv_s);
+    bool wall;
+    int face;
+    int j = neighbour<-L::ex[A], -L::ey[A], -L::ez[A], C>(g, x, y, z, wall, face);
+    constexpr int O = opp_dir(A, L::H);
+    if (!wall) return Store<T>::load(slot[O - 1][j], inv_s);
+    return Store<T>::load(slot[A - 1][i], inv_s) + g.wt[A][face];
+  }
+};
+
+template <int DIM, class T, int PAR, int A>
+struct StoreDir {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  __device__ __forceinline__ static void run(T* const* slot, const Geo<C>& g, int x, int y, int z,
+                                             int i, C v, C inv_s) {
+    constexpr int O = opp_dir(A, L::H);
+    if (PAR == 0) {
+      slot[O - 1][i] = Store<T>::save(v, inv_s);
+      return;
+    }
+    bool wall;
+    int face;
+    int j = neighbour<L::ex[A], L::ey[A], L::ez[A], C>(g, x, y, z, wall, face);
+    if (!wall)
+      slot[A - 1][j] = Store<T>::save(v, inv_s);
+    else
+      slot[O - 1][i] = Store<T>::save(v - g.wt[A][face], inv_s);
+  }
+};
+
+template <int DIM, class T, int PAR, int A = 1>
+__device__ __forceinline__ void load_all(T* const* slot, const Geo<typename Store<T>::C>& g, int x,
+                                         int y, int z, int i, typename Store<T>::C inv_s,
+                                         typename Store<T>::C* f) {
+  if constexpr (A < Lat<DIM>::Q) {
+    f[A] = LoadDir<DIM, T, PAR, A>::run(slot, g, x, y, z, i, inv_s);
+    load_all<DIM, T, PAR, A + 1>(slot, g, x, y, z, i, inv_s, f);
+  }
+}
+
+template <int DIM, class T, int PAR, int A = 1>
+__device__ __forceinline__ void store_all(T* const* slot, const Geo<typename Store<T>::C>& g, int x,
+                                          int y, int z, int i, typename Store<T>::C inv_s,
+                                          const typename Store<T>::C* f) {
+  if constexpr (A < Lat<DIM>::Q) {
+    StoreDir<DIM, T, PAR, A>::run(slot, g, x, y, z, i, f[A], inv_s);
+    store_all<DIM, T, PAR, A + 1>(slot, g, x, y, z, i, inv_s, f);
+  }
+}
+
+// u* = sum_a e_a f_a / rho0 (Eq. 5) and S = sum_{a>=1} f_a
+template <int DIM, class C>
+__device__ __forceinline__ void moments(const C* f, C rho0, C& S, C* us) {
+  using L = Lat<DIM>;
+  C s = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int a = 1; a < L::Q; a++) {
+    s += f[a];
+    if (L::ex[a] != 0) jx += L::ex[a] * f[a];
+    if (L::ey[a] != 0) jy += L::ey[a] * f[a];
+    if (DIM == 3 && L::ez[a] != 0) jz += L::ez[a] * f[a];
+  }
+  C ir = C(1) / rho0;
+  S = s;
+  us[0] = jx * ir;
+  us[1] = jy * ir;
+  us[2] = DIM == 3 ? jz * ir : C(0);
+}
+
+struct SlotPtrs {
+  void* p[18];
+};
+
+template <int DIM, class T>
+__device__ __forceinline__ void slots_of(const SlotPtrs& sp, T** s) {
+#pragma unroll
+  for (int a = 0; a < Lat<DIM>::Q - 1; a++) s[a] = reinterpret_cast<T*>(sp.p[a]);
+}
+
+template <class C>
+struct K1Args {
+  Geo<C> g;
+  SlotPtrs slot;
+  const uint32_t* bflag;
+  const C* facc;
+  int vd;
+  C omega, kforce, rho0, body[3];
+  C inv_s;
+  int nsegx;
+  int nbx, bx_shift, nblk, xcd_per;
+};
+
+// Fused collision (Eq. 1 with Eqs. 4-8), half-way bounce-back and A-A streaming.
+template <int DIM, class T, int PAR, int BX>
+__global__ __launch_bounds__(BX) void k_collide_stream(K1Args<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  // XCD-aware order: consecutive logical blocks (adjacent rows) share an XCD and its L2
+  int b = blockIdx.x;
+  int lb = a.xcd_per > 0 ? (b & 7) * a.xcd_per + (b >> 3) : b;
+  int bx = lb % a.nbx, row = lb / a.nbx;
+  int x = bx * BX + threadIdx.x;
+  int y = row % a.g.n[1], z = row / a.g.n[1];
+  if (x >= a.g.n[0]) return;
+  int i = x + a.g.n[0] * row;
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  C f[L::Q];
+  load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+  C S, us[3];
+  moments<DIM, C>(f, a.rho0, S, us);
+  const C w0 = C(L::w[0]);
+  // Eq. 6 with u*
+  C p = (C(1) / C(3)) / (C(1) - w0) *
+        (S - a.rho0 * w0 * (us[0] * us[0] + us[1] * us[1] + us[2] * us[2]) * C(1.5));
+  // IB force where the band flag is set, plus the uniform body force
+  C ff[3] = {a.body[0], a.body[1], a.body[2]};
+  if (a.bflag[x / SEG + a.nsegx * row] != 0u) {
+    const C* fa = a.facc + (size_t)i * a.vd;
+    ff[0] += fa[0];
+    ff[1] += fa[1];
+    if (DIM == 3) ff[2] += fa[2];
+  }
+  C hr = C(0.5) / a.rho0;
+  C u[3] = {us[0] + ff[0] * hr, us[1] + ff[1] * hr, DIM == 3 ? us[2] + ff[2] * hr : C(0)};  // Eq. 7
+  C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  C uf = u[0] * ff[0] + u[1] * ff[1] + u[2] * ff[2];
+  C post[L::Q];
+  // equilibrium (Eq. 4) and forcing (Eq. 8) split into parts even and odd in e_a
+  // (Eqs. 37-40): opposite directions share the even part.
+#pragma unroll
+  for (int d = 1; d <= L::H; d++) {
+    const int o = d + L::H;
+    C eu = L::ex[d] * u[0] + L::ey[d] * u[1] + (DIM == 3 ? L::ez[d] * u[2] : C(0));
+    C ef = L::ex[d] * ff[0] + L::ey[d] * ff[1] + (DIM == 3 ? L::ez[d] * ff[2] : C(0));
+    C wd = C(L::w[d]);
+    C ce = wd * (C(3) * p + a.rho0 * (C(4.5) * eu * eu - C(1.5) * uu));
+    C oe = wd * a.rho0 * C(3) * eu;
+    C cf = a.kforce * wd * (C(9) * eu * ef - C(3) * uf);
+    C of = a.kforce * wd * C(3) * ef;
+    post[d] = f[d] - a.omega * (f[d] - (ce + oe)) + (cf + of);
+    post[o] = f[o] - a.omega * (f[o] - (ce - oe)) + (cf - of);
+  }
+  store_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, post);
+}
+
+template <class C>
+struct K2Args {
+  Geo<C> g;
+  SlotPtrs slot;
+  const int* seglist;
+  const int* segcount;
+  C* ustar;
+  C* facc;
+  int vd, nsegx;
+  C inv_s;
+  int* status;
+};
+
+// Band pass: at the nodes of every flagged segment compute u* from the PDFs in the
+// current A-A layout, and clear the force accumulator.
+template <int DIM, class T, int PAR>
+__global__ __launch_bounds__(256) void k_band_prep(K2Args<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  int count = *a.segcount;
+  int lane = threadIdx.x & (SEG - 1);
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  int groups = gridDim.x * (blockDim.x / SEG);
+  bool bad = false;
+  for (int s = blockIdx.x * (blockDim.x / SEG) + threadIdx.x / SEG; s < count; s += groups) {
+    int seg = a.seglist[s];
+    int sx = seg % a.nsegx, row = seg / a.nsegx;
+    int x = sx * SEG + lane;
+    if (x >= a.g.n[0]) continue;
+    int y = row % a.g.n[1], z = row / a.g.n[1];
+    int i = x + a.g.n[0] * row;
+    C f[L::Q];
+    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+    C S, us[3];
+    moments<DIM, C>(f, a.g.rho0, S, us);
+    C* u = a.ustar + (size_t)i * a.vd;
+    C* fa = a.facc + (size_t)i * a.vd;
+    u[0] = us[0];
+    u[1] = us[1];
+    fa[0] = 0;
+    fa[1] = 0;
+    if (DIM == 3) {
+      u[2] = us[2];
+      fa[2] = 0;
+    }
+    bad |= !(us[0] == us[0]) || !(us[1] == us[1]) || !(us[2] == us[2]);
+  }
+  if (bad) atomicOr(a.status, ST_NAN);
+}
+
+template <class C>
+struct GatherArgs {
+  Geo<C> g;
+  SlotPtrs slot;
+  const uint32_t* bflag;
+  const C* facc;
+  int vd, nsegx;
+  C inv_s;
+  double *p, *u, *force, *fout;
+};
+
+// natural-order gather of p, u* (Eqs. 5-6), the band force, and/or all PDFs
+template <int DIM, class T, int PAR>
+__global__ void k_gather(GatherArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.N) return;
+  int x = int(i % a.g.n[0]), row = int(i / a.g.n[0]);
+  int y = row % a.g.n[1], z = row / a.g.n[1];
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  C f[L::Q];
+  load_all<DIM, T, PAR>(slot, a.g, x, y, z, int(i), a.inv_s, f);
+  if (a.fout)
+    for (int d = 1; d < L::Q; d++) a.fout[(size_t)(d - 1) * a.g.N + i] = double(f[d]);
+  C S, us[3];
+  moments<DIM, C>(f, a.g.rho0, S, us);
+  const double w0 = L::w[0];
+  double uu = double(us[0]) * us[0] + double(us[1]) * us[1] + double(us[2]) * us[2];
+  if (a.p) a.p[i] = (1.0 / 3.0) / (1.0 - w0) * (double(S) - double(a.g.rho0) * w0 * uu * 1.5);
+  for (int c = 0; c < DIM; c++) {
+    if (a.u) a.u[(size_t)c * a.g.N + i] = double(us[c]);
+    if (a.force)
+      a.force[(size_t)c * a.g.N + i] =
+          a.bflag[x / SEG + a.nsegx * row] ? double(a.facc[(size_t)i * a.vd + c]) : 0.0;
+  }
+}
+
+template <class C>
+struct ScatterArgs {
+  Geo<C> g;
+  SlotPtrs slot;
+  C inv_s;
+  const double *fin, *p, *u;
+};
+
+// write PDFs in the natural (even) layout: given values, or f_eq(p, u) of Eq. 4
+template <int DIM, class T>
+__global__ void k_scatter(ScatterArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.N) return;
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  if (a.fin) {
+    for (int d = 1; d < L::Q; d++)
+      slot[d - 1][i] = Store<T>::save(C(a.fin[(size_t)(d - 1) * a.g.N + i]), a.inv_s);
+    return;
+  }
+  double p = a.p ? a.p[i] : 0.0;
+  double u[3] = {0, 0, 0};
+  if (a.u)
+    for (int c = 0; c < DIM; c++) u[c] = a.u[(size_t)c * a.g.N + i];
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double rho0 = double(a.g.rho0);
+  for (int d = 1; d < L::Q; d++) {
+    double eu = L::ex[d] * u[0] + L::ey[d] * u[1] + L::ez[d] * u[2];
+    double feq = 3.0 * L::w[d] * p + rho0 * L::w[d] * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    slot[d - 1][i] = Store<T>::save(C(feq), a.inv_s);
+  }
+}
+
+template <class C>
+struct InteriorArgs {
+  Geo<C> g;
+  SlotPtrs slot;
+  C inv_s;
+  const double *X, *D;
+  double *P, *L;
+};
+
+// Momentum and angular momentum of the fluid inside each particle volume,
+// P = sum chi rho0 u*, L = sum chi (x - X_c) x rho0 u*, with chi = clamp(R + 1/2 - |x - X_c|,
+// 0, 1): the interior-fluid terms F_f, T_f of Eqs. 14-15 are their changes per step.
+// One workgroup per particle, FP64 accumulation and a fixed-order reduction.
+template <int DIM, class T, int PAR>
+__global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  __shared__ double red[6][256];
+  int p = blockIdx.x;
+  double Xc[3] = {a.X[3 * p], a.X[3 * p + 1], DIM == 3 ? a.X[3 * p + 2] : 0.0};
+  double R = 0.5 * a.D[p];
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; d++) {
+    lo[d] = max(int(floor(Xc[d] - R - 0.5)), 0);
+    hi[d] = min(int(ceil(Xc[d] + R + 0.5)), a.g.n[d] - 1);
+  }
+  int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
+  int total = (wx > 0 && wy > 0 && wz > 0) ? wx * wy * wz : 0;
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double rho0 = double(a.g.rho0);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int x = lo[0] + t % wx, y = lo[1] + (t / wx) % wy, z = lo[2] + t / (wx * wy);
+    double r[3] = {x - Xc[0], y - Xc[1], DIM == 3 ? z - Xc[2] : 0.0};
+    double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double chi = R + 0.5 - sqrt(d2);
+    if (chi <= 0.0) continue;
+    chi = chi > 1.0 ? 1.0 : chi;
+    int i = x + a.g.n[0] * (y + a.g.n[1] * z);
+    C f[L::Q];
+    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+    C S, us[3];
+    moments<DIM, C>(f, a.g.rho0, S, us);
+    double m[3] = {chi * (rho0 * double(us[0])), chi * (rho0 * double(us[1])),
+                   DIM == 3 ? chi * (rho0 * double(us[2])) : 0.0};
+    acc[0] += m[0];
+    acc[1] += m[1];
+    acc[2] += m[2];
+    acc[3] += r[1] * m[2] - r[2] * m[1];
+    acc[4] += r[2] * m[0] - r[0] * m[2];
+    acc[5] += r[0] * m[1] - r[1] * m[0];
+  }
+  for (int k = 0; k < 6; k++) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 6; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; k++) {
+      a.P[3 * p + k] = red[k][0];
+      a.L[3 * p + k] = red[3 + k][0];
+    }
+}
+
+template <class C>
+Geo<C> make_geo(const iblbm_ctx* c) {
+  Geo<C> g;
+  for (int a = 0; a < 3; a++) {
+    g.n[a] = c->cfg.n[a];
+    g.periodic[a] = c->cfg.periodic[a];
+  }
+  g.N = c->N;
+  g.rho0 = C(c->cfg.rho0);
+  const int* ex = c->dim == 2 ? Lat<2>::ex : Lat<3>::ex;
+  const int* ey = c->dim == 2 ? Lat<2>::ey : Lat<3>::ey;
+  const int* ez = c->dim == 2 ? Lat<2>::ez : Lat<3>::ez;
+  const double* w = c->dim == 2 ? Lat<2>::w : Lat<3>::w;
+  for (int d = 0; d < 19; d++)
+    for (int fc = 0; fc < 6; fc++) {
+      double v = 0;
+      if (d < c->q) {
+        double eu = ex[d] * c->cfg.wall_u[fc][0] + ey[d] * c->cfg.wall_u[fc][1] +
+                    ez[d] * c->cfg.wall_u[fc][2];
+        v = 2.0 * w[d] * c->cfg.rho0 * eu * 3.0;
+      }
+      g.wt[d][fc] = C(v);
+    }
+  return g;
+}
+
+SlotPtrs make_slots(const iblbm_ctx* c) {
+  SlotPtrs s;
+  for (int a = 0; a < 18; a++)
+    s.p[a] = a < c->q - 1 ? (char*)c->f + (size_t)a * c->N * c->sbytes : nullptr;
+  return s;
+}
+
+template <class T>
+typename Store<T>::C inv_scale(const iblbm_ctx* c) {
+  return c->storage == IBLBM_F16 ? typename Store<T>::C(1.0 / c->cfg.f16_scale)
+                                 : typename Store<T>::C(1);
+}
+
+// dispatch over (dim, storage) to a functor templated on <DIM, T>
+template <template <int, class> class F, class... Args>
+void dispatch(iblbm_ctx* c, Args... args) {
+  if (c->dim == 2) {
+    switch (c->storage) {
+      case IBLBM_F64: F<2, double>::run(c, args...); break;
+      case IBLBM_F32: F<2, float>::run(c, args...); break;
+      case IBLBM_BF16: F<2, bf16s>::run(c, args...); break;
+      default: F<2, __half>::run(c, args...); break;
+    }
+  } else {
+    switch (c->storage) {
+      case IBLBM_F64: F<3, double>::run(c, args...); break;
+      case IBLBM_F32: F<3, float>::run(c, args...); break;
+      case IBLBM_BF16: F<3, bf16s>::run(c, args...); break;
+      default: F<3, __half>::run(c, args...); break;
+    }
+  }
+}
+
+template <int DIM, class T>
+struct RunCollide {
+  template <int BX>
+  static void go(iblbm_ctx* c, K1Args<typename Store<T>::C>& a) {
+    a.nbx = (c->cfg.n[0] + BX - 1) / BX;
+    a.nblk = a.nbx * c->cfg.n[1] * c->cfg.n[2];
+    a.xcd_per = (a.nblk % 8 == 0) ? a.nblk / 8 : 0;
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_collide_stream<DIM, T, 0, BX>), dim3(a.nblk), dim3(BX), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_collide_stream<DIM, T, 1, BX>), dim3(a.nblk), dim3(BX), 0, c->stream, a);
+  }
+  static void run(iblbm_ctx* c) {
+    using C = typename Store<T>::C;
+    K1Args<C> a;
+    a.g = make_geo<C>(c);
+    a.slot = make_slots(c);
+    a.bflag = c->bflag;
+    a.facc = (const C*)c->facc;
+    a.vd = c->vd;
+    a.omega = C(1.0 / c->cfg.tau);
+    a.kforce = C(1.0 - 0.5 / c->cfg.tau);
+    a.rho0 = C(c->cfg.rho0);
+    for (int k = 0; k < 3; k++) a.body[k] = k < DIM ? C(c->cfg.body_force[k]) : C(0);
+    a.inv_s = inv_scale<T>(c);
+    a.nsegx = (int)c->nsegx;
+    int nx = c->cfg.n[0];
+    if (nx % 256 == 0 || nx > 1024)
+      go<256>(c, a);
+    else if (nx % 128 == 0)
+      go<128>(c, a);
+    else
+      go<64>(c, a);
+  }
+};
+
+template <int DIM, class T>
+struct RunBand {
+  static void run(iblbm_ctx* c) {
+    using C = typename Store<T>::C;
+    K2Args<C> a;
+    a.g = make_geo<C>(c);
+    a.slot = make_slots(c);
+    a.seglist = c->seglist;
+    a.segcount = c->segcount;
+    a.ustar = (C*)c->ustar;
+    a.facc = (C*)c->facc;
+    a.vd = c->vd;
+    a.nsegx = (int)c->nsegx;
+    a.inv_s = inv_scale<T>(c);
+    a.status = c->dstatus;
+    long long maxseg = c->nseg;
+    int blocks = (int)std::min<long long>(4096, (maxseg + 15) / 16);
+    if (blocks < 1) blocks = 1;
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_band_prep<DIM, T, 0>), dim3(blocks), dim3(256), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_band_prep<DIM, T, 1>), dim3(blocks), dim3(256), 0, c->stream, a);
+  }
+};
+
+template <int DIM, class T>
+struct RunGather {
+  static void run(iblbm_ctx* c, double* p, double* u, double* force, double* fout) {
+    using C = typename Store<T>::C;
+    GatherArgs<C> a;
+    a.g = make_geo<C>(c);
+    a.slot = make_slots(c);
+    a.bflag = c->bflag;
+    a.facc = (const C*)c->facc;
+    a.vd = c->vd;
+    a.nsegx = (int)c->nsegx;
+    a.inv_s = inv_scale<T>(c);
+    a.p = p;
+    a.u = u;
+    a.force = force;
+    a.fout = fout;
+    unsigned blocks = unsigned((c->N + 255) / 256);
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_gather<DIM, T, 0>), dim3(blocks), dim3(256), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_gather<DIM, T, 1>), dim3(blocks), dim3(256), 0, c->stream, a);
+  }
+};
+
+template <int DIM, class T>
+struct RunScatter {
+  static void run(iblbm_ctx* c, const double* fin, const double* p, const double* u) {
+    using C = typename Store<T>::C;
+    ScatterArgs<C> a;
+    a.g = make_geo<C>(c);
+    a.slot = make_slots(c);
+    a.inv_s = inv_scale<T>(c);
+    a.fin = fin;
+    a.p = p;
+    a.u = u;
+    unsigned blocks = unsigned((c->N + 255) / 256);
+    hipLaunchKernelGGL((k_scatter<DIM, T>), dim3(blocks), dim3(256), 0, c->stream, a);
+  }
+};
+
+template <int DIM, class T>
+struct RunInterior {
+  static void run(iblbm_ctx* c, double* P, double* Lm) {
+    using C = typename Store<T>::C;
+    InteriorArgs<C> a;
+    a.g = make_geo<C>(c);
+    a.slot = make_slots(c);
+    a.inv_s = inv_scale<T>(c);
+    a.X = c->X;
+    a.D = c->D;
+    a.P = P;
+    a.L = Lm;
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_interior<DIM, T, 0>), dim3(c->np), dim3(256), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_interior<DIM, T, 1>), dim3(c->np), dim3(256), 0, c->stream, a);
+  }
+};
+
+}  // namespace
+
+void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L) {
+  if (c->np > 0) dispatch<RunInterior>(c, P, L);
+}
+
+void lbm_collide_stream(iblbm_ctx* c) { dispatch<RunCollide>(c); }
+void lbm_band_prep(iblbm_ctx* c) { dispatch<RunBand>(c); }
+void lbm_get_fields(iblbm_ctx* c, double* p, double* u, double* force) {
+  dispatch<RunGather>(c, p, u, force, (double*)nullptr);
+}
+void lbm_get_pdfs(iblbm_ctx* c, double* f) {
+  dispatch<RunGather>(c, (double*)nullptr, (double*)nullptr, (double*)nullptr, f);
+}
+void lbm_set_pdfs(iblbm_ctx* c, const double* f) {
+  dispatch<RunScatter>(c, f, (const double*)nullptr, (const double*)nullptr);
+  c->parity = 0;
+}
+void lbm_init_equilibrium(iblbm_ctx* c, const double* p, const double* u) {
+  dispatch<RunScatter>(c, (const double*)nullptr, p, u);
+  c->parity = 0;
+}

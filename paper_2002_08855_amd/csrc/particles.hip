@@ -1,0 +1,337 @@
+// Particle kernels for gfx950: cell list and pair search (Sec. 5, Eqs. 49-51), the
+// short-range pair force (Eq. 16), hydrodynamic loads and Newton-Euler motion
+// (Sec. 2.3, Eqs. 14-15).  Everything here is FP64.
+//
+// Cells are at least (D_max + zeta)/2 wide (Eq. 50), so every partner of a particle
+// lies in the 5^d block of cells around its own.  A cell holds up to CELL_CAP centres
+// (Eq. 49 keeps it at one for non-overlapping particles).  Pair tests and forces are
+// evaluated with contraction off, so they round exactly like a plain sequential
+// program; each particle sums its partner forces in ascending partner order, which
+// makes the result independent of thread scheduling.
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+struct PartArgs {
+  int np, dim;
+  int n[3], nc[3], periodic[3];
+  double invh[3];
+  double zeta, eps_pp, E_pp, rho0;
+  double g[3];
+  const double *X, *D, *cb;
+  double *U, *Om, *Fh, *Th, *Fc, *Xw, *M, *I;
+  int* cell_count;
+  int* cell_items;
+  int* cell_of;
+  int *pair_up, *pair_nup;
+  int* status;
+};
+
+__device__ __forceinline__ int cell_coord(double x, double invh, int nc) {
+  int c = int(floor((x + 0.5) * invh));
+  return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+// Cell of every particle and a slot in it.  Lanes of a wavefront that fall into the
+// same cell take one atomic between them: ballot the lanes matching the leader's cell,
+// let the leader add the popcount, and rank the others by their position in the mask.
+__global__ void k_cells(PartArgs a) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = p < a.np;
+  long long id = -1;
+  if (act) {
+    int c[3] = {0, 0, 0};
+    for (int d = 0; d < a.dim; d++) c[d] = cell_coord(a.X[3 * p + d], a.invh[d], a.nc[d]);
+    for (int d = 0; d < 3; d++) a.cell_of[3 * p + d] = c[d];
+    id = c[0] + (long long)a.nc[0] * (c[1] + (long long)a.nc[1] * c[2]);
+  }
+  unsigned long long pending = __ballot(act);
+  int lane = threadIdx.x & 63;
+  while (pending) {
+    int leader = __ffsll((long long)pending) - 1;
+    long long lid = __shfl(id, leader, 64);
+    unsigned long long same = __ballot(act && id == lid) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&a.cell_count[lid], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) {
+      int rank = base + __popcll(same & ((1ull << lane) - 1ull));
+      if (rank < CELL_CAP)
+        a.cell_items[lid * CELL_CAP + rank] = p;
+      else
+        atomicOr(a.status, ST_CELL_OVERFLOW);
+    }
+    pending &= ~same;
+  }
+}
+
+// Eq. 16: magnitude of the repulsion along the unit vector from the partner
+__device__ double pair_mag(double d, double D, double zeta, double c, double eps, double E) {
+  if (d >= D + zeta) return 0.0;
+  double s = (d - D - zeta) / zeta;
+  double F = c / eps * (s * s);
+  if (d < D) F = F + c / E * ((D - d) / zeta);
+  return F;
+}
+
+constexpr int MAXP = 32;
+
+// Partners of each particle from the 5^d cell block, the pair force on it summed in
+// ascending partner order (pairs first, then the wall images in face order), and its
+// partners j > i for the pair list.
+__global__ void k_pairs(PartArgs a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  int nb[MAXP];
+  int cnt = 0;
+  bool over = false;
+  const double* Xi = a.X + 3 * i;
+  int ci[3] = {a.cell_of[3 * i], a.cell_of[3 * i + 1], a.cell_of[3 * i + 2]};
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; d++) {
+    lo[d] = d < a.dim ? max(ci[d] - 2, 0) : 0;
+    hi[d] = d < a.dim ? min(ci[d] + 2, a.nc[d] - 1) : 0;
+  }
+  for (int cz = lo[2]; cz <= hi[2]; cz++)
+    for (int cy = lo[1]; cy <= hi[1]; cy++)
+      for (int cx = lo[0]; cx <= hi[0]; cx++) {
+        long long id = cx + (long long)a.nc[0] * (cy + (long long)a.nc[1] * cz);
+        int m = min(a.cell_count[id], CELL_CAP);
+        for (int s = 0; s < m; s++) {
+          int j = a.cell_items[id * CELL_CAP + s];
+          if (j == i) continue;
+          const double* Xj = a.X + 3 * j;
+          double d2 = 0.0;
+          for (int d = 0; d < a.dim; d++) {
+            double dx = Xi[d] - Xj[d];
+            d2 = d2 + dx * dx;
+          }
+          double sr = 0.5 * (a.D[i] + a.D[j]) + a.zeta;
+          if (d2 < sr * sr) {
+            if (cnt < MAXP) {
+              // insertion into the ascending list
+              int k = cnt++;
+              while (k > 0 && nb[k - 1] > j) {
+                nb[k] = nb[k - 1];
+                k--;
+              }
+              nb[k] = j;
+            } else {
+              over = true;
+            }
+          }
+        }
+      }
+  double F[3] = {0.0, 0.0, 0.0};
+  int nup = 0;
+  for (int k = 0; k < cnt; k++) {
+    int j = nb[k];
+    int pa = i < j ? i : j, pb = i < j ? j : i;
+    double dx[3] = {0.0, 0.0, 0.0}, d2 = 0.0;
+    for (int d = 0; d < a.dim; d++) {
+      dx[d] = a.X[3 * pa + d] - a.X[3 * pb + d];
+      d2 = d2 + dx[d] * dx[d];
+    }
+    double dist = sqrt(d2);
+    double mag = pair_mag(dist, 0.5 * (a.D[pa] + a.D[pb]), a.zeta, 0.5 * (a.cb[pa] + a.cb[pb]),
+                          a.eps_pp, a.E_pp);
+    for (int d = 0; d < a.dim; d++) {
+      double Fa = mag * (dx[d] / dist);
+      F[d] = i == pa ? F[d] + Fa : F[d] - Fa;
+    }
+    if (j > i) {
+      if (nup < PAIR_CAP)
+        a.pair_up[i * PAIR_CAP + nup] = j;
+      else
+        over = true;
+      nup++;
+    }
+  }
+  // walls: Eq. 16 against the mirror image in each wall plane (at -1/2 and n - 1/2)
+  for (int d = 0; d < a.dim; d++) {
+    if (a.periodic[d]) continue;
+    for (int side = 0; side < 2; side++) {
+      double h = side == 0 ? Xi[d] + 0.5 : (a.n[d] - 0.5) - Xi[d];
+      double mag = pair_mag(2.0 * h, a.D[i], a.zeta, a.cb[i], a.eps_pp, a.E_pp);
+      if (mag != 0.0) F[d] = F[d] + (side == 0 ? mag : -mag);
+    }
+  }
+  for (int d = 0; d < 3; d++) a.Fc[3 * i + d] = F[d];
+  a.pair_nup[i] = min(nup, PAIR_CAP);
+  if (over) atomicOr(a.status, ST_PAIR_OVERFLOW);
+}
+
+template <class C>
+struct LoadArgs {
+  PartArgs pa;
+  const int *mstart, *mcount;
+  const double* mr;
+  const double* mdV;
+  const C* mF;
+  C* mFprev;
+  const double *Pin, *Lin;
+  double *Pprev, *Lprev, *Hprev, *Gprev;
+  const double *M, *V, *I;
+  double* X;
+  int update;  // 0: loads only
+};
+
+// One workgroup per particle: F_h = -sum F_k dV_k, T_h = -sum r_k x F_k dV_k in FP64 with a
+// fixed reduction tree, then Eqs. 14-15 with the interior-fluid terms
+// F_f = P^n - P^(n-1), T_f = L^n - L^(n-1), the hydrodynamic load averaged over the
+// current and previous steps, explicit Euler for U, Omega and the trapezoid rule for X.
+template <class C>
+__global__ __launch_bounds__(256) void k_loads_newton(LoadArgs<C> a) {
+  __shared__ double red[6][256];
+  int p = blockIdx.x;
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    const double* r = a.mr + 4 * (size_t)k;
+    const C* Fk = a.mF + 4 * (size_t)k;
+    double dV = a.mdV[k];
+    double Fd[3] = {double(Fk[0]) * dV, double(Fk[1]) * dV,
+                    a.pa.dim == 3 ? double(Fk[2]) * dV : 0.0};
+    acc[0] -= Fd[0];
+    acc[1] -= Fd[1];
+    acc[2] -= Fd[2];
+    acc[3] -= r[1] * Fd[2] - r[2] * Fd[1];
+    acc[4] -= r[2] * Fd[0] - r[0] * Fd[2];
+    acc[5] -= r[0] * Fd[1] - r[1] * Fd[0];
+    if (a.update) {
+      C* Fp = a.mFprev + 4 * (size_t)k;
+      Fp[0] = Fk[0];
+      Fp[1] = Fk[1];
+      Fp[2] = Fk[2];
+    }
+  }
+  for (int k = 0; k < 6; k++) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 6; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const PartArgs& q = a.pa;
+  for (int d = 0; d < 3; d++) {
+    q.Fh[3 * p + d] = red[d][0];
+    q.Th[3 * p + d] = red[3 + d][0];
+  }
+  if (!a.update) return;
+  double meff = a.M[p] - q.rho0 * a.V[p];
+  bool bad = false;
+  for (int d = 0; d < q.dim; d++) {
+    double U0 = q.U[3 * p + d];
+    double H = red[d][0] + (a.Pin[3 * p + d] - a.Pprev[3 * p + d]);
+    double Havg = 0.5 * (H + a.Hprev[3 * p + d]);
+    double U1 = U0 + (Havg + q.Fc[3 * p + d] + meff * q.g[d]) / a.M[p];
+    a.Hprev[3 * p + d] = H;
+    q.U[3 * p + d] = U1;
+    a.X[3 * p + d] = a.X[3 * p + d] + 0.5 * (U0 + U1);
+    bad |= !(U1 == U1) || fabs(U1) > 1.0;
+  }
+  for (int d = (q.dim == 2 ? 2 : 0); d < 3; d++) {
+    double G = red[3 + d][0] + (a.Lin[3 * p + d] - a.Lprev[3 * p + d]);
+    double Gavg = 0.5 * (G + a.Gprev[3 * p + d]);
+    a.Gprev[3 * p + d] = G;
+    q.Om[3 * p + d] = q.Om[3 * p + d] + Gavg / a.I[p];
+    bad |= !(q.Om[3 * p + d] == q.Om[3 * p + d]);
+  }
+  for (int d = 0; d < 3; d++) {
+    a.Pprev[3 * p + d] = a.Pin[3 * p + d];
+    a.Lprev[3 * p + d] = a.Lin[3 * p + d];
+  }
+  // empty this particle's cell for the next cell-list build
+  int c0 = q.cell_of[3 * p], c1 = q.cell_of[3 * p + 1], c2 = q.cell_of[3 * p + 2];
+  q.cell_count[c0 + (long long)q.nc[0] * (c1 + (long long)q.nc[1] * c2)] = 0;
+  if (bad) atomicOr(q.status, ST_NAN);
+}
+
+__global__ void k_zero_cells(PartArgs a) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  int c0 = a.cell_of[3 * p], c1 = a.cell_of[3 * p + 1], c2 = a.cell_of[3 * p + 2];
+  a.cell_count[c0 + (long long)a.nc[0] * (c1 + (long long)a.nc[1] * c2)] = 0;
+}
+
+PartArgs make_pargs(iblbm_ctx* c) {
+  PartArgs a;
+  a.np = c->np;
+  a.dim = c->dim;
+  for (int d = 0; d < 3; d++) {
+    a.n[d] = c->cfg.n[d];
+    a.nc[d] = c->nc[d];
+    a.periodic[d] = c->cfg.periodic[d];
+    a.invh[d] = c->invh[d];
+    a.g[d] = c->cfg.gravity[d];
+  }
+  a.zeta = c->cfg.zeta;
+  a.eps_pp = c->cfg.eps_pp;
+  a.E_pp = c->cfg.E_pp;
+  a.rho0 = c->cfg.rho0;
+  a.X = c->X;
+  a.D = c->D;
+  a.cb = c->cb;
+  a.U = c->U;
+  a.Om = c->Om;
+  a.Fh = c->Fh;
+  a.Th = c->Th;
+  a.Fc = c->Fc;
+  a.cell_count = c->cell_count;
+  a.cell_items = c->cell_items;
+  a.cell_of = c->cell_of;
+  a.pair_up = c->pair_up;
+  a.pair_nup = c->pair_nup;
+  a.status = c->dstatus;
+  return a;
+}
+
+template <class C>
+void run_loads(iblbm_ctx* c, int update) {
+  LoadArgs<C> a;
+  a.pa = make_pargs(c);
+  a.mstart = c->mstart;
+  a.mcount = c->mcount;
+  a.mr = c->mr;
+  a.mdV = c->mdV;
+  a.mF = (const C*)c->mF;
+  a.mFprev = (C*)c->mFprev;
+  a.Pin = c->Pin;
+  a.Lin = c->Lin;
+  a.Pprev = c->Pprev;
+  a.Lprev = c->Lprev;
+  a.Hprev = c->Hprev;
+  a.Gprev = c->Gprev;
+  a.M = c->M;
+  a.V = c->V;
+  a.I = c->I;
+  a.X = c->X;
+  a.update = update;
+  hipLaunchKernelGGL((k_loads_newton<C>), dim3(c->np), dim3(256), 0, c->stream, a);
+}
+
+}  // namespace
+
+// cells of the current positions and the pair forces (F_c) at those positions
+void part_cells_pairs(iblbm_ctx* c) {
+  if (c->np == 0) return;
+  PartArgs a = make_pargs(c);
+  int blocks = (c->np + 255) / 256;
+  hipLaunchKernelGGL(k_cells, dim3(blocks), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, c->stream, a);
+}
+
+// loads and the Newton-Euler update (which also empties the cells used this step)
+void part_loads_newton(iblbm_ctx* c) {
+  if (c->np == 0) return;
+  if (c->fp64) run_loads<double>(c, 1); else run_loads<float>(c, 1);
+}
+
+void part_zero_cells(iblbm_ctx* c) {
+  if (c->np == 0) return;
+  PartArgs a = make_pargs(c);
+  hipLaunchKernelGGL(k_zero_cells, dim3((c->np + 255) / 256), dim3(256), 0, c->stream, a);
+}
