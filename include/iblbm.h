@@ -100,7 +100,7 @@ typedef struct {
   int64_t n_pairs;           /* pairs i<j within D_ij + zeta at the last step */
   int32_t flags;             /* device status bits (1 cell overflow, 2 pair overflow, 4 NaN) */
   int32_t fallbacks;         /* learned forcing: steps that fell back to MDF */
-  int64_t band_segments;     /* 16-node row segments flagged as IB band, last step */
+  int64_t band_nodes;        /* nodes inside some point's support at the last step */
   double time_ms[IBLBM_NGROUPS];   /* accumulated kernel time per group (timing on) */
   int64_t launches[IBLBM_NGROUPS]; /* kernel launches per group (timing on) */
 } iblbm_stats;
@@ -152,9 +152,14 @@ iblbm_status iblbm_get_pairs(iblbm_ctx* ctx, int32_t* ij, int64_t cap, int64_t* 
 iblbm_status iblbm_get_cells(iblbm_ctx* ctx, int32_t* cell, int32_t* dims);
 iblbm_status iblbm_get_stats(iblbm_ctx* ctx, iblbm_stats* out);
 iblbm_status iblbm_num_particles(iblbm_ctx* ctx, int32_t* np, int32_t* n_markers);
-/* Enable per-kernel-group HIP-event timing on the library's stream (0 = off). */
-iblbm_status iblbm_set_timing(iblbm_ctx* ctx, int32_t on);
+/* HIP-event timing on the library's stream: 0 = off, 1 = every kernel group, otherwise
+ * a bit mask over iblbm_timer groups (bit g times group g).  Events bracket each
+ * launch of a timed group; the elapsed times accumulate into iblbm_stats. */
+iblbm_status iblbm_set_timing(iblbm_ctx* ctx, int32_t mask);
 iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
+#define IBLBM_OPT_IBM_LDS 1 /* 1 (default): per-particle LDS interpolation/spreading kernels;
+                               0: the point-wise kernels with global atomics */
+iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
 /* Capture each step as a HIP graph and replay it (0 = plain launches). */
 iblbm_status iblbm_set_graph(iblbm_ctx* ctx, int32_t on);
 

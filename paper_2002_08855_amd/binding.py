@@ -43,7 +43,7 @@ class Stats(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("slip_rms", C.c_double), ("truncated", C.c_int64),
         ("n_pairs", C.c_int64), ("flags", C.c_int32), ("fallbacks", C.c_int32),
-        ("band_segments", C.c_int64), ("time_ms", C.c_double * 8), ("launches", C.c_int64 * 8),
+        ("band_nodes", C.c_int64), ("time_ms", C.c_double * 8), ("launches", C.c_int64 * 8),
     ]
 
 
@@ -91,6 +91,7 @@ def lib():
             "iblbm_set_timing": (C.c_int, [vp, C.c_int32]),
             "iblbm_reset_stats": (C.c_int, [vp]),
             "iblbm_set_graph": (C.c_int, [vp, C.c_int32]),
+            "iblbm_set_option": (C.c_int, [vp, C.c_int32, C.c_int32]),
             "iblbm_set_mlp": (C.c_int, [vp, _f, _f]),
             "iblbm_capture_samples": (C.c_int, [vp, _f, _f]),
             "iblbm_nn_train": (C.c_int, [_f, _f, C.c_int64, _f, _P(TrainOpts), _f]),
@@ -283,11 +284,18 @@ class Sim:
         d["launches"] = dict(zip(TIMERS, list(s.launches)))
         return d
 
-    def set_timing(self, on=True):
-        self._check(lib().iblbm_set_timing(self.h, int(on)))
+    def set_timing(self, mask=1):
+        """0 off, 1 all kernel groups, else a bit mask over TIMERS."""
+        self._check(lib().iblbm_set_timing(self.h, int(mask)))
 
     def reset_stats(self):
         self._check(lib().iblbm_reset_stats(self.h))
+
+    def set_option(self, option, value):
+        self._check(lib().iblbm_set_option(self.h, int(option), int(value)))
+
+    def set_ibm_lds(self, on=True):
+        self.set_option(1, int(on))
 
     def set_graph(self, on=True):
         self._check(lib().iblbm_set_graph(self.h, int(on)))

@@ -116,10 +116,13 @@ struct iblbm_ctx {
   void* ustar = nullptr;    // band u*, N x VD compute type
   void* facc = nullptr;     // IB force density, N x VD compute type
   int vd = 2;               // vector stride of ustar / facc (2 in 2-D, 4 in 3-D)
-  uint32_t* bflag = nullptr;  // nseg flags
+  uint32_t* bmap = nullptr;   // 2 x nwords band bitmaps (bit per node), one per step parity
+  long long nwords = 0, nwx = 0;  // words per bitmap, 32-node words per row
+  int fbuf = 0;               // bitmap of the most recent step
+  bool band_pending = false;  // the next interpolation pass builds the band
+  uint32_t* bflag = nullptr;  // nseg segment flags (per-point fallback band)
   int* seglist = nullptr;     // flagged segments
-  int* segcount = nullptr;    // two counters used alternately (see ibm_clear_and_mark)
-  int segcur = 0;             // index of the counter that holds the current count
+  int* segcount = nullptr;    // number of listed segments
   long long nseg = 0, nsegx = 0;
   // particles (FP64)
   int np = 0, capp = 0;
@@ -132,7 +135,9 @@ struct iblbm_ctx {
   std::vector<double> hD, hX;  // host copies used for validation
   std::vector<int> hcount;
   double dmax = 0.0;
-  int max_box = 0;  // max marker-stencil box side for LDS binning
+  int box_cap = 0;     // nodes in the largest per-particle support box
+  int lds_max = 65536; // LDS bytes a workgroup may use on this device
+  bool ibm_lds = true; // per-particle LDS kernels for interpolation and spreading
   // markers
   int nmk = 0, capm = 0;
   int* mown = nullptr;
@@ -163,6 +168,8 @@ struct iblbm_ctx {
   float* feat = nullptr;      // nmk x 10 scratch
   // timing
   bool timing = false;
+  int timing_mask = 0;  // bit g: time kernel group g
+  bool t_open = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_group;
   size_t ev_used = 0;
@@ -190,8 +197,8 @@ void lbm_set_pdfs(iblbm_ctx* c, const double* df);
 void lbm_get_pdfs(iblbm_ctx* c, double* df);
 void lbm_get_fields(iblbm_ctx* c, double* dp, double* du, double* dforce);
 void lbm_collide_stream(iblbm_ctx* c);
-void lbm_band_prep(iblbm_ctx* c);
-void ibm_clear_and_mark(iblbm_ctx* c);
+void ibm_band(iblbm_ctx* c);
+bool ibm_uses_lds(const iblbm_ctx* c);
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode);
 void ibm_spread(iblbm_ctx* c, int use_set);
 void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L);

@@ -167,16 +167,14 @@ void flush_timing(iblbm_ctx* c) {
 
 void enqueue_step(iblbm_ctx* c) {
   bool parts = c->np > 0;
-  tbegin(c, IBLBM_T_BAND);
-  ibm_clear_and_mark(c);
-  tend(c);
+  c->fbuf = (int)(c->step & 1);
   if (parts) {
     tbegin(c, IBLBM_T_PARTICLE);
     part_cells_pairs(c);
     tend(c);
-    tbegin(c, IBLBM_T_BAND);
-    lbm_band_prep(c);
-    tend(c);
+    if (!ibm_uses_lds(c)) tbegin(c, IBLBM_T_BAND);
+    ibm_band(c);
+    if (!ibm_uses_lds(c)) tend(c);
     if (c->cfg.forcing == IBLBM_FORCING_LEARNED && c->has_mlp) {
       mlp_step_forcing(c);
     } else {
@@ -217,7 +215,9 @@ void enqueue_step(iblbm_ctx* c) {
 }  // namespace
 
 void tbegin(iblbm_ctx* c, int group) {
-  if (!c->timing) return;
+  c->t_open = false;
+  if (!c->timing || !((c->timing_mask >> group) & 1)) return;
+  c->t_open = true;
   if (c->ev_used + 2 > c->ev.size()) {
     for (int k = 0; k < 64; k++) {
       hipEvent_t e;
@@ -232,7 +232,8 @@ void tbegin(iblbm_ctx* c, int group) {
 }
 
 void tend(iblbm_ctx* c) {
-  if (!c->timing) return;
+  if (!c->timing || !c->t_open) return;
+  c->t_open = false;
   c->ev_group[c->ev_used] = -1;
   HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
   c->ev_used++;
@@ -269,6 +270,7 @@ iblbm_status iblbm_create(const iblbm_config* cfg, iblbm_ctx** out) {
   c->vd = c->dim == 2 ? 2 : 4;
   try {
     HIPCHK(hipGetDevice(&c->device));
+    HIPCHK(hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     if (cfg->stream) {
       c->stream = (hipStream_t)cfg->stream;
     } else {
@@ -283,8 +285,11 @@ iblbm_status iblbm_create(const iblbm_config* cfg, iblbm_ctx** out) {
     c->nsegx = (c->cfg.n[0] + SEG - 1) / SEG;
     c->nseg = c->nsegx * c->cfg.n[1] * c->cfg.n[2];
     c->bflag = dzeros<uint32_t>(c, (size_t)c->nseg);
+    c->nwx = (c->cfg.n[0] + 31) / 32;
+    c->nwords = c->nwx * c->cfg.n[1] * c->cfg.n[2];
+    c->bmap = dzeros<uint32_t>(c, 2 * (size_t)c->nwords);
     c->seglist = dzeros<int>(c, (size_t)c->nseg);
-    c->segcount = dzeros<int>(c, 2);
+    c->segcount = dzeros<int>(c, 1);
     c->dstatus = dzeros<int>(c, 8);
     c->dstats = dzeros<double>(c, 4);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -489,6 +494,14 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     c->hX = allX;
     c->hD = allD;
     c->hcount.insert(c->hcount.end(), mcount.begin(), mcount.end());
+    // per-particle support box of the largest particle (4-point kernel: at most
+    // floor(D) + 5 nodes per axis)
+    {
+      double dmax = 0;
+      for (double d : allD) dmax = std::max(dmax, d);
+      int B = (int)floor(dmax) + 5;
+      c->box_cap = dim == 2 ? B * B : B * B * B;
+    }
     // cell grid (Eqs. 49-50) and pair buffers
     double H = compute_H(c);
     long long ncell = 1;
@@ -655,15 +668,19 @@ iblbm_status iblbm_get_stats(iblbm_ctx* c, iblbm_stats* o) {
   memset(o, 0, sizeof(*o));
   try {
     HIPCHK(hipSetDevice(c->device));
-    int st[4], cnt[2];
+    int st[4];
+    std::vector<uint32_t> bm((size_t)c->nwords);
     HIPCHK(hipMemcpyAsync(st, c->dstatus, sizeof(st), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(cnt, c->segcount, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(bm.data(), c->bmap + (size_t)c->fbuf * c->nwords, bm.size() * 4,
+                          hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    long long band = 0;
+    for (uint32_t w : bm) band += __builtin_popcount(w);
     o->flags = st[0];
     unsigned long long t;
     memcpy(&t, st + 2, sizeof(t));
     o->truncated = (long long)t;
-    o->band_segments = cnt[c->segcur];
+    o->band_nodes = band;
     int64_t npairs = 0;
     iblbm_get_pairs(c, nullptr, 0, &npairs);
     o->n_pairs = npairs;
@@ -687,9 +704,10 @@ iblbm_status iblbm_num_particles(iblbm_ctx* c, int32_t* np, int32_t* nmk) {
   return IBLBM_OK;
 }
 
-iblbm_status iblbm_set_timing(iblbm_ctx* c, int32_t on) {
+iblbm_status iblbm_set_timing(iblbm_ctx* c, int32_t mask) {
   if (!c) return IBLBM_E_ARG;
-  c->timing = on != 0;
+  c->timing = mask != 0;
+  c->timing_mask = mask == 1 ? 0xff : mask;
   return IBLBM_OK;
 }
 
@@ -701,6 +719,16 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* c) {
   }
   c->ev_used = 0;
   return IBLBM_OK;
+}
+
+iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
+  if (!c) return IBLBM_E_ARG;
+  if (option == IBLBM_OPT_IBM_LDS) {
+    c->ibm_lds = value != 0;
+    c->graph_dirty = true;
+    return IBLBM_OK;
+  }
+  return fail(c, IBLBM_E_ARG, "unknown option");
 }
 
 iblbm_status iblbm_set_graph(iblbm_ctx* c, int32_t on) {

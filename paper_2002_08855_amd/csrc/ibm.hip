@@ -1,16 +1,29 @@
 // Immersed-boundary kernels for gfx950 (Sec. 2.2 and Sec. 4 of the paper).
 //
 // Each Lagrangian point touches the nodes of its delta-function support only
-// (Eqs. 47-48).  A wavefront serves one point in 3-D (4x4x4 = 64 support nodes, one per
-// lane) and four points in 2-D (16 lanes each): lane loads, weights and the reduction
-// are all independent of the other points, so interpolation is a gather plus a
-// cross-lane sum, and spreading is a set of float atomics into the band force buffer.
-// Band bookkeeping: before the forcing, every 16-node row segment that some support
-// touches is flagged (and listed once), so that u* is computed and the force cleared
-// only there, and the collision reads the force only there.
-#include "common.h"
+// (Eqs. 47-48).  Two implementations share the arithmetic:
+//
+//  - per particle (default): all points of a particle lie at distance R from its
+//    centre, so their supports fit in one box of side floor(Xc+R) - floor(Xc-R) + 4.
+//    One workgroup per particle keeps that box in LDS.  Interpolation marks the touched
+//    nodes, stages u + f/(2 rho0) of exactly those nodes into LDS and gathers every
+//    support from LDS; spreading accumulates all contributions with LDS atomics and
+//    adds each touched node to the global force once.  The first forcing pass of a
+//    step also computes u* (Eq. 5) from the PDFs at the touched nodes, stores it for
+//    the later passes, clears the force there and records the touched nodes in the
+//    band bitmap that tells the collision where a force is present.
+//  - per point (fallback when the box does not fit in LDS): one wavefront serves one
+//    point in 3-D (4x4x4 support nodes, a lane each) and four points in 2-D; the band
+//    is built beforehand as a list of 16-node row segments.
+//
+// In the per-particle kernels one lane owns one point: it evaluates the twelve 1-D
+// weights of its support once and walks the 4x4x4 support, accumulating in registers
+// (interpolation) or with LDS atomics (spreading).
+#include "pdf_access.h"
 
 namespace {
+
+using namespace pdf;
 
 template <class C>
 __device__ __forceinline__ C phi(int kind, C r) {
@@ -31,39 +44,6 @@ struct MarkerGeo {
   int dim, kind, width;
 };
 
-// The support node handled by lane l of a point at X: returns the node index or -1
-// (outside a wall axis), and its weight.
-template <int DIM, class C>
-__device__ __forceinline__ int support_node(const MarkerGeo& g, const double* X, int l, C& w,
-                                            bool& trunc) {
-  int id[3] = {l & 3, (l >> 2) & 3, (l >> 4) & 3};
-  w = C(1);
-  trunc = false;
-  int c[3] = {0, 0, 0};
-  bool inside_support = true;
-#pragma unroll
-  for (int a = 0; a < DIM; a++) {
-    if (id[a] >= g.width) inside_support = false;
-    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
-    int cc = lo + id[a];
-    w *= phi<C>(g.kind, C(double(cc) - X[a]));
-    if (cc < 0 || cc >= g.n[a]) {
-      if (g.periodic[a]) {
-        cc = cc < 0 ? cc + g.n[a] : cc - g.n[a];
-      } else {
-        trunc = true;
-      }
-    }
-    c[a] = cc;
-  }
-  if (!inside_support) {
-    trunc = false;
-    return -1;
-  }
-  if (trunc) return -1;
-  return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
-}
-
 struct PartView {
   const double *X, *U, *Om;
   const int* mown;
@@ -71,7 +51,6 @@ struct PartView {
   const double* mdV;
 };
 
-template <class C>
 __device__ __forceinline__ void marker_pos_vel(const PartView& P, int k, double* X, double* Ub,
                                                int dim) {
   int p = P.mown[k];
@@ -87,11 +66,47 @@ __device__ __forceinline__ void marker_pos_vel(const PartView& P, int k, double*
   Ub[2] = dim == 3 ? Uc[2] + (W[0] * r[1] - W[1] * r[0]) : 0.0;
 }
 
+// The support node handled by lane l of a point at X: node index or -1 (outside a
+// wall axis, or a lane beyond the support width), its weight, and whether it was cut
+// by a wall.
+template <int DIM, class C>
+__device__ __forceinline__ int support_node(const MarkerGeo& g, const double* X, int l, C& w,
+                                            bool& trunc) {
+  int id[3] = {l & 3, (l >> 2) & 3, (l >> 4) & 3};
+  w = C(1);
+  trunc = false;
+  int c[3] = {0, 0, 0};
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    if (id[a] >= g.width) inside = false;
+    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
+    int cc = lo + id[a];
+    w *= phi<C>(g.kind, C(double(cc) - X[a]));
+    if (cc < 0 || cc >= g.n[a]) {
+      if (g.periodic[a])
+        cc = cc < 0 ? cc + g.n[a] : cc - g.n[a];
+      else
+        trunc = true;
+    }
+    c[a] = cc;
+  }
+  if (!inside) {
+    trunc = false;
+    return -1;
+  }
+  if (trunc) return -1;
+  return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+}
+
 template <class C>
 __device__ __forceinline__ C group_sum(C v, int G) {
   for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+// ---------------------------------------------------------------------------
+// per-point kernels (fallback)
 
 template <class C>
 struct InterpArgs {
@@ -110,40 +125,12 @@ struct InterpArgs {
   float* feat;  // nmk x 10
 };
 
-// mode 0: multi-direct-forcing pass (Eqs. 9-10): dF = 2 rho0 (U_b - D_I u), F += dF.
+// mode 0: a multi-direct-forcing pass (Eqs. 9-10): dF = 2 rho0 (U_b - D_I u), F += dF.
 // mode 1: accumulate |U_b - D_I u|^2 for the slip statistic.
-// mode 2: write U_b - D_I u* into the learned-force features.
-template <int DIM, class C>
-__global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
-  constexpr int G = DIM == 3 ? 64 : 16;
-  int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
-  int l = threadIdx.x & (G - 1);
-  int k = gid;
-  bool active = k < a.nmk;
-  double X[3] = {0, 0, 0}, Ub[3] = {0, 0, 0};
-  if (active) marker_pos_vel<C>(a.P, k, X, Ub, DIM);
-  C acc[3] = {0, 0, 0};
-  bool tr = false;
-  if (active) {
-    C w;
-    int i = support_node<DIM, C>(a.g, X, l, w, tr);
-    if (i >= 0) {
-      const C* u = a.ustar + (size_t)i * a.vd;
-      const C* f = a.facc + (size_t)i * a.vd;
-      acc[0] = w * (u[0] + f[0] * a.half_inv_rho);
-      acc[1] = w * (u[1] + f[1] * a.half_inv_rho);
-      if (DIM == 3) acc[2] = w * (u[2] + f[2] * a.half_inv_rho);
-    }
-  }
-  for (int c = 0; c < DIM; c++) acc[c] = group_sum(acc[c], G);
-  if (a.first_pass && a.mode == 0) {
-    unsigned long long m = __ballot(tr);
-    if (l == 0 && m) {
-      unsigned long long mine = G == 64 ? m : (m >> (threadIdx.x & 63 & ~(G - 1))) & ((1ull << G) - 1);
-      if (mine) atomicAdd(a.trunc, (unsigned long long)__popcll(mine));
-    }
-  }
-  if (!active || l != 0) return;
+// mode 2: write U_b - D_I u into the learned-force features.
+template <class C>
+__device__ __forceinline__ void point_result(const InterpArgs<C>& a, int k, const double* Ub,
+                                             const C* acc, int DIM) {
   if (a.mode == 0) {
     C* F = a.F + 4 * (size_t)k;
     C* dF = a.dF + 4 * (size_t)k;
@@ -160,8 +147,41 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
     }
     atomicAdd(a.slip2, s);
   } else {
-    for (int c = 0; c < 3; c++) a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
+    for (int c = 0; c < 3; c++)
+      a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
   }
+}
+
+template <int DIM, class C>
+__global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
+  constexpr int G = DIM == 3 ? 64 : 16;
+  int k = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  int l = threadIdx.x & (G - 1);
+  bool active = k < a.nmk;
+  double X[3] = {0, 0, 0}, Ub[3] = {0, 0, 0};
+  if (active) marker_pos_vel(a.P, k, X, Ub, DIM);
+  C acc[3] = {0, 0, 0};
+  bool tr = false;
+  if (active) {
+    C w;
+    int i = support_node<DIM, C>(a.g, X, l, w, tr);
+    if (i >= 0) {
+      const C* u = a.ustar + (size_t)i * a.vd;
+      const C* f = a.facc + (size_t)i * a.vd;
+      for (int c = 0; c < DIM; c++) acc[c] = w * (u[c] + f[c] * a.half_inv_rho);
+    }
+  }
+  for (int c = 0; c < DIM; c++) acc[c] = group_sum(acc[c], G);
+  if (a.first_pass && a.mode == 0) {
+    unsigned long long m = __ballot(tr);
+    if (l == 0 && m) {
+      unsigned long long mine =
+          G == 64 ? m : (m >> (threadIdx.x & 63 & ~(G - 1))) & ((1ull << G) - 1);
+      if (mine) atomicAdd(a.trunc, (unsigned long long)__popcll(mine));
+    }
+  }
+  if (!active || l != 0) return;
+  point_result<C>(a, k, Ub, acc, DIM);
 }
 
 template <class C>
@@ -182,7 +202,7 @@ __global__ __launch_bounds__(256) void k_spread(SpreadArgs<C> a) {
   int l = threadIdx.x & (G - 1);
   if (k >= a.nmk) return;
   double X[3] = {0, 0, 0}, Ub[3];
-  marker_pos_vel<C>(a.P, k, X, Ub, DIM);
+  marker_pos_vel(a.P, k, X, Ub, DIM);
   C w;
   bool tr;
   int i = support_node<DIM, C>(a.g, X, l, w, tr);
@@ -190,9 +210,7 @@ __global__ __launch_bounds__(256) void k_spread(SpreadArgs<C> a) {
   C s = w * C(a.P.mdV[k]);
   const C* dF = a.dF + 4 * (size_t)k;
   C* f = a.facc + (size_t)i * a.vd;
-  unsafeAtomicAdd(f + 0, dF[0] * s);
-  unsafeAtomicAdd(f + 1, dF[1] * s);
-  if (DIM == 3) unsafeAtomicAdd(f + 2, dF[2] * s);
+  for (int c = 0; c < DIM; c++) unsafeAtomicAdd(f + c, dF[c] * s);
 }
 
 struct MarkArgs {
@@ -202,17 +220,16 @@ struct MarkArgs {
   const int *mstart, *mcount;
   uint32_t* bflag;
   int* seglist;
-  int* count_new;
+  int* count;
   int nsegx;
+  int words;  // LDS bitmap words: segments x rows of the largest particle's box
 };
 
-constexpr int MARK_WORDS = 2048;
-
-// One workgroup per particle: collect the row segments touched by the supports of its
-// points in an LDS bitmap, then flag and list each new segment once.
+// Fallback band: one workgroup per particle collects the row segments touched by the
+// supports of its points in an LDS bitmap, then flags and lists each new segment once.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_mark(MarkArgs a) {
-  __shared__ uint32_t bits[MARK_WORDS];
+  extern __shared__ uint32_t bits[];
   __shared__ int box[6];
   int p = blockIdx.x;
   int m0 = a.mstart[p], mc = a.mcount[p];
@@ -233,35 +250,17 @@ __global__ __launch_bounds__(256) void k_mark(MarkArgs a) {
     box[4] = lo[2];
     box[5] = hi[2];
   }
-  for (int w = threadIdx.x; w < MARK_WORDS; w += blockDim.x) bits[w] = 0;
+  for (int w = threadIdx.x; w < a.words; w += blockDim.x) bits[w] = 0;
   __syncthreads();
   int nsx = box[1] - box[0] + 1, ny = box[3] - box[2] + 1, nz = box[5] - box[4] + 1;
   long long nbits = (long long)nsx * ny * nz;
-  if (nbits > 32LL * MARK_WORDS || nsx <= 0 || ny <= 0 || nz <= 0) {
-    // degenerate or oversized box: flag every touched segment directly
-    for (int t = threadIdx.x; t < mc * 16; t += blockDim.x) {
-      int k = m0 + t / 16, row = t % 16;
-      double X[3], Ub[3];
-      marker_pos_vel<double>(a.P, k, X, Ub, DIM);
-      int l0[3];
-      for (int d = 0; d < DIM; d++)
-        l0[d] = a.g.kind == 0 ? int(floor(X[d])) - 1 : int(floor(X[d] + 0.5)) - 1;
-      int yy = l0[1] + (row & 3), zz = DIM == 3 ? l0[2] + (row >> 2) : 0;
-      if ((row & 3) >= a.g.width || (DIM == 3 && (row >> 2) >= a.g.width) || (DIM == 2 && row >= 4)) continue;
-      if (yy < 0 || yy >= a.g.n[1] || zz < 0 || zz >= a.g.n[2]) continue;
-      int xa = max(l0[0], 0), xb = min(l0[0] + a.g.width - 1, a.g.n[0] - 1);
-      for (int sx = xa / SEG; sx <= xb / SEG && xa <= xb; sx++) {
-        int seg = sx + a.nsegx * (yy + a.g.n[1] * zz);
-        if (atomicOr(&a.bflag[seg], 1u) == 0u) a.seglist[atomicAdd(a.count_new, 1)] = seg;
-      }
-    }
-    return;
-  }
+  bool direct = nbits > 32LL * a.words || nsx <= 0 || ny <= 0 || nz <= 0;
   for (int t = threadIdx.x; t < mc * 16; t += blockDim.x) {
     int k = m0 + t / 16, row = t % 16;
-    if ((row & 3) >= a.g.width || (DIM == 3 && (row >> 2) >= a.g.width) || (DIM == 2 && row >= 4)) continue;
+    if ((row & 3) >= a.g.width || (DIM == 3 && (row >> 2) >= a.g.width) || (DIM == 2 && row >= 4))
+      continue;
     double X[3], Ub[3];
-    marker_pos_vel<double>(a.P, k, X, Ub, DIM);
+    marker_pos_vel(a.P, k, X, Ub, DIM);
     int l0[3] = {0, 0, 0};
     for (int d = 0; d < DIM; d++)
       l0[d] = a.g.kind == 0 ? int(floor(X[d])) - 1 : int(floor(X[d] + 0.5)) - 1;
@@ -270,27 +269,379 @@ __global__ __launch_bounds__(256) void k_mark(MarkArgs a) {
     int xa = max(l0[0], 0), xb = min(l0[0] + a.g.width - 1, a.g.n[0] - 1);
     if (xa > xb) continue;
     for (int sx = xa / SEG; sx <= xb / SEG; sx++) {
-      long long bit = (long long)(sx - box[0]) + nsx * ((long long)(yy - box[2]) + ny * (zz - box[4]));
-      atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+      if (direct) {
+        int seg = sx + a.nsegx * (yy + a.g.n[1] * zz);
+        if (atomicOr(&a.bflag[seg], 1u) == 0u) a.seglist[atomicAdd(a.count, 1)] = seg;
+      } else {
+        long long bit = (long long)(sx - box[0]) + nsx * ((long long)(yy - box[2]) + ny * (zz - box[4]));
+        atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+      }
     }
   }
   __syncthreads();
+  if (direct) return;
   for (long long bit = threadIdx.x; bit < nbits; bit += blockDim.x) {
     if (!((bits[bit >> 5] >> (bit & 31)) & 1u)) continue;
     int sx = int(bit % nsx) + box[0];
     long long r = bit / nsx;
     int yy = int(r % ny) + box[2], zz = int(r / ny) + box[4];
     int seg = sx + a.nsegx * (yy + a.g.n[1] * zz);
-    if (atomicOr(&a.bflag[seg], 1u) == 0u) a.seglist[atomicAdd(a.count_new, 1)] = seg;
+    if (atomicOr(&a.bflag[seg], 1u) == 0u) a.seglist[atomicAdd(a.count, 1)] = seg;
   }
 }
 
-// clear the flags listed at the previous step and reset the append counter
-__global__ void k_clear(uint32_t* bflag, const int* seglist, const int* count_old, int* count_new) {
-  int n = *count_old;
+// clear the segment flags listed at the previous step and reset the list
+__global__ void k_clear(uint32_t* bflag, const int* seglist, int* count) {
+  int n = *count;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
     bflag[seglist[s]] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *count_new = 0;
+}
+__global__ void k_reset_count(int* count) { *count = 0; }
+
+// ---------------------------------------------------------------------------
+// per-particle kernels
+
+template <int DIM>
+struct PBox {
+  int lo[3], B[3], n;
+};
+
+template <int DIM>
+__device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, int kind) {
+  PBox<DIM> b;
+  b.n = 1;
+  for (int d = 0; d < 3; d++) {
+    if (d < DIM) {
+      int lo = kind == 0 ? int(floor(Xc[d] - R)) - 1 : int(floor(Xc[d] - R + 0.5)) - 1;
+      int hi = kind == 0 ? int(floor(Xc[d] + R)) + 2 : int(floor(Xc[d] + R + 0.5)) + 1;
+      b.lo[d] = lo;
+      b.B[d] = hi - lo + 1;
+    } else {
+      b.lo[d] = 0;
+      b.B[d] = 1;
+    }
+    b.n *= b.B[d];
+  }
+  return b;
+}
+
+// support node of lane l as a box-local index (or -1: outside the walls or the box)
+template <int DIM, class C>
+__device__ __forceinline__ int support_local(const MarkerGeo& g, const PBox<DIM>& b,
+                                             const double* X, int l, C& w, bool& trunc) {
+  int id[3] = {l & 3, (l >> 2) & 3, (l >> 4) & 3};
+  w = C(1);
+  trunc = false;
+  bool inside = true;
+  int loc[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    if (id[a] >= g.width) inside = false;
+    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
+    int cc = lo + id[a];
+    w *= phi<C>(g.kind, C(double(cc) - X[a]));
+    if (cc < 0 || cc >= g.n[a]) trunc = true;
+    loc[a] = cc - b.lo[a];
+    if (loc[a] < 0 || loc[a] >= b.B[a]) inside = false;
+  }
+  if (!inside) {
+    trunc = false;
+    return -1;
+  }
+  if (trunc) return -1;
+  return loc[0] + b.B[0] * (loc[1] + b.B[1] * loc[2]);
+}
+
+template <class C>
+struct LdsArgs {
+  MarkerGeo g;
+  PartView P;
+  const double* D;
+  const int *mstart, *mcount;
+  int cap;  // node capacity of the LDS box arrays
+  C* ustar;
+  C* facc;
+  int vd;
+  C half_inv_rho, two_rho;
+  C* F;
+  C* dF;
+  int first_pass, mode;
+  unsigned long long* trunc;
+  double* slip2;
+  float* feat;
+  uint32_t* bmap;  // band bitmap of this step (bit per node, 32-node words per row)
+  int nwx;         // words per row
+  // PDF access for the first pass
+  Geo<C> geo;
+  SlotPtrs slot;
+  C inv_s;
+};
+
+constexpr int LDS_THREADS = 1024;
+
+// Support of one point seen by the lane that owns it: the first node, the 1-D weights
+// phi(x - X) per axis (Eq. 12: the 2-D/3-D kernel is their product), which nodes lie
+// inside the walls, and the offset of the first node in the particle's box.
+template <int DIM, class C>
+struct Support {
+  int lo[3];
+  C w[3][4];
+  bool ok[3][4];
+  int box0;  // box-local index of the first node
+  int ntr;   // nodes outside the walls
+};
+
+template <int DIM, class C>
+__device__ __forceinline__ void point_support(const MarkerGeo& g, const PBox<DIM>& b,
+                                              const double* X, Support<DIM, C>& s) {
+  s.ntr = 0;
+  int loc[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      s.w[a][q] = C(a < DIM && q < g.width ? 0 : (q == 0 ? 1 : 0));
+      s.ok[a][q] = a >= DIM ? q == 0 : false;
+    }
+    s.lo[a] = 0;
+    if (a >= DIM) continue;
+    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
+    s.lo[a] = lo;
+    loc[a] = lo - b.lo[a];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q >= g.width) continue;
+      int cc = lo + q;
+      s.w[a][q] = phi<C>(g.kind, C(double(cc) - X[a]));
+      // inside the walls and inside the particle's box
+      s.ok[a][q] = cc >= 0 && cc < g.n[a] && loc[a] + q >= 0 && loc[a] + q < b.B[a];
+    }
+  }
+  s.box0 = loc[0] + b.B[0] * (loc[1] + b.B[1] * loc[2]);
+  int nin[3] = {0, 0, 0}, wdt[3] = {1, 1, 1};
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    wdt[a] = g.width;
+#pragma unroll
+    for (int q = 0; q < 4; q++) nin[a] += (q < g.width && s.ok[a][q]) ? 1 : 0;
+  }
+  if (DIM == 2) nin[2] = 1;
+  s.ntr = wdt[0] * wdt[1] * wdt[2] - nin[0] * nin[1] * nin[2];
+}
+
+// visit every support node inside the walls: fn(box-local index, weight)
+template <int DIM, class C, class Fn>
+__device__ __forceinline__ void for_support(const Support<DIM, C>& s, const PBox<DIM>& b, int width,
+                                            Fn fn) {
+  const int W2 = DIM == 3 ? 4 : 1;
+#pragma unroll
+  for (int iz = 0; iz < W2; iz++) {
+    if (DIM == 3 && (iz >= width || !s.ok[2][iz])) continue;
+#pragma unroll
+    for (int iy = 0; iy < 4; iy++) {
+      if (iy >= width || !s.ok[1][iy]) continue;
+      C wyz = s.w[1][iy] * (DIM == 3 ? s.w[2][iz] : C(1));
+      int row = s.box0 + b.B[0] * (iy + b.B[1] * iz);
+#pragma unroll
+      for (int ix = 0; ix < 4; ix++) {
+        if (ix >= width || !s.ok[0][ix]) continue;
+        // (phi_x phi_y) phi_z, the product order of Eq. 12
+        C w = DIM == 3 ? (s.w[0][ix] * s.w[1][iy]) * s.w[2][iz] : s.w[0][ix] * s.w[1][iy];
+        (void)wyz;
+        fn(row + ix, w);
+      }
+    }
+  }
+}
+
+// Interpolation (+ point force) for one forcing pass, one lane per point; FIRST also
+// computes u* at the touched nodes and builds the band.
+template <int DIM, class T, int PAR, int FIRST>
+__global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  extern __shared__ double smem_d[];
+  C* ub = reinterpret_cast<C*>(smem_d);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(ub + DIM * a.cap);
+  int p = blockIdx.x;
+  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
+  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
+  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
+  int nw = (b.n + 31) >> 5;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) bits[t] = 0u;
+  __syncthreads();
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  // each lane owns points k = m0 + threadIdx.x, + blockDim.x, ...; keep the first two
+  // supports in registers across the phases (more points per lane are recomputed)
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    Support<DIM, C> s;
+    point_support<DIM, C>(a.g, b, X, s);
+    for_support<DIM, C>(s, b, a.g.width,
+                        [&](int loc, C) { atomicOr(&bits[loc >> 5], 1u << (loc & 31)); });
+  }
+  __syncthreads();
+  // stage u (first pass: u* from the PDFs, Eq. 5; later: u* + f/(2 rho0), Eq. 7)
+  T* slot[L::Q - 1];
+  if (FIRST) slots_of<DIM, T>(a.slot, slot);
+  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
+    if (!((bits[t >> 5] >> (t & 31)) & 1u)) continue;
+    int x = b.lo[0] + t % b.B[0];
+    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
+    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+    int i = x + a.g.n[0] * (y + a.g.n[1] * z);
+    C* us = a.ustar + (size_t)i * a.vd;
+    if (FIRST) {
+      C f[L::Q];
+      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, i, a.inv_s, f);
+      C S, u[3];
+      moments<DIM, C>(f, a.geo.rho0, S, u);
+      C* fa = a.facc + (size_t)i * a.vd;
+#pragma unroll
+      for (int c = 0; c < DIM; c++) {
+        ub[c * a.cap + t] = u[c];
+        us[c] = u[c];
+        fa[c] = C(0);
+      }
+    } else {
+      const C* fa = a.facc + (size_t)i * a.vd;
+#pragma unroll
+      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = us[c] + fa[c] * a.half_inv_rho;
+    }
+  }
+  if (FIRST) {
+    // band bitmap: one atomic per (row, 32-node word) of the box
+    int rows = b.B[1] * b.B[2];
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+      int y = b.lo[1] + r % b.B[1], z = b.lo[2] + r / b.B[1];
+      if (y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
+      int w0 = (b.lo[0] >= 0 ? b.lo[0] : 0) >> 5;
+      uint32_t m[3] = {0u, 0u, 0u};
+      for (int xl = 0; xl < b.B[0]; xl++) {
+        int t = xl + b.B[0] * r;
+        if (!((bits[t >> 5] >> (t & 31)) & 1u)) continue;
+        int x = b.lo[0] + xl;
+        int wi = (x >> 5) - w0;
+        if (wi >= 0 && wi < 3) m[wi] |= 1u << (x & 31);
+      }
+      uint32_t* row = a.bmap + (size_t)a.nwx * (y + a.g.n[1] * z);
+      for (int wi = 0; wi < 3; wi++)
+        if (m[wi]) atomicOr(row + w0 + wi, m[wi]);
+    }
+  }
+  __syncthreads();
+  // gather each support from LDS (Eq. 9 with Eq. 12) and form the point force (Eq. 10)
+  unsigned long long ntr = 0;
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    Support<DIM, C> s;
+    point_support<DIM, C>(a.g, b, X, s);
+    ntr += s.ntr;
+    C acc[3] = {0, 0, 0};
+    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C w) {
+#pragma unroll
+      for (int c = 0; c < DIM; c++) acc[c] += w * ub[c * a.cap + loc];
+    });
+    if (a.mode == 0) {
+      C* F = a.F + 4 * (size_t)k;
+      C* dF = a.dF + 4 * (size_t)k;
+      for (int c = 0; c < DIM; c++) {
+        C d = a.two_rho * (C(Ub[c]) - acc[c]);
+        dF[c] = d;
+        F[c] = a.first_pass ? d : F[c] + d;
+      }
+    } else if (a.mode == 1) {
+      double s2 = 0;
+      for (int c = 0; c < DIM; c++) {
+        double e = Ub[c] - double(acc[c]);
+        s2 += e * e;
+      }
+      atomicAdd(a.slip2, s2);
+    } else {
+      for (int c = 0; c < 3; c++)
+        a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
+    }
+  }
+  if (a.first_pass && a.mode == 0 && ntr) atomicAdd(a.trunc, ntr);
+}
+
+// Spreading of one forcing pass (Eq. 11 with Eq. 13), one lane per point, through the
+// particle's LDS box; each touched node then reaches the global force once.
+template <int DIM, class C>
+__global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
+  extern __shared__ double smem_d[];
+  C* box = reinterpret_cast<C*>(smem_d);
+  int p = blockIdx.x;
+  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
+  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
+  if (b.n > a.cap) return;
+  for (int t = threadIdx.x; t < b.n; t += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < DIM; c++) box[c * a.cap + t] = C(0);
+  __syncthreads();
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    Support<DIM, C> s;
+    point_support<DIM, C>(a.g, b, X, s);
+    const C* d = a.dF + 4 * (size_t)k;
+    C dV = C(a.P.mdV[k]);
+    C Fk[3] = {d[0], d[1], DIM == 3 ? d[2] : C(0)};
+    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C w) {
+      C sw = w * dV;
+#pragma unroll
+      for (int c = 0; c < DIM; c++) atomicAdd(&box[c * a.cap + loc], Fk[c] * sw);
+    });
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
+    int x = b.lo[0] + t % b.B[0];
+    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
+    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+    if (x < 0 || x >= a.g.n[0] || y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
+    C* f = a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
+#pragma unroll
+    for (int c = 0; c < DIM; c++) {
+      C v = box[c * a.cap + t];
+      if (v != C(0)) unsafeAtomicAdd(f + c, v);
+    }
+  }
+}
+
+// Fallback band u*: at the nodes of every listed segment compute u* from the PDFs,
+// clear the force, and mark the segment's nodes in the band bitmap.
+template <int DIM, class T, int PAR>
+__global__ __launch_bounds__(256) void k_band_prep(LdsArgs<typename Store<T>::C> a,
+                                                    const int* seglist, const int* count, int nsegx) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  int n = *count;
+  int lane = threadIdx.x & (SEG - 1);
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  int groups = gridDim.x * (blockDim.x / SEG);
+  for (int s = blockIdx.x * (blockDim.x / SEG) + threadIdx.x / SEG; s < n; s += groups) {
+    int seg = seglist[s];
+    int sx = seg % nsegx, row = seg / nsegx;
+    int x = sx * SEG + lane;
+    if (lane == 0) atomicOr(a.bmap + (size_t)a.nwx * row + (x >> 5), 0xffffu << (x & 31));
+    if (x >= a.g.n[0]) continue;
+    int y = row % a.g.n[1], z = row / a.g.n[1];
+    int i = x + a.g.n[0] * row;
+    C f[L::Q];
+    load_all<DIM, T, PAR>(slot, a.geo, x, y, z, i, a.inv_s, f);
+    C S, us[3];
+    moments<DIM, C>(f, a.geo.rho0, S, us);
+    C* u = a.ustar + (size_t)i * a.vd;
+    C* fa = a.facc + (size_t)i * a.vd;
+    for (int c = 0; c < DIM; c++) {
+      u[c] = us[c];
+      fa[c] = C(0);
+    }
+  }
 }
 
 MarkerGeo make_mgeo(const iblbm_ctx* c) {
@@ -316,8 +667,8 @@ PartView make_pview(const iblbm_ctx* c) {
   return P;
 }
 
-template <int DIM, class C>
-void run_interp(iblbm_ctx* c, int first, int mode) {
+template <class C>
+InterpArgs<C> make_interp_args(iblbm_ctx* c, int first, int mode) {
   InterpArgs<C> a;
   a.g = make_mgeo(c);
   a.P = make_pview(c);
@@ -334,13 +685,117 @@ void run_interp(iblbm_ctx* c, int first, int mode) {
   a.trunc = (unsigned long long*)(c->dstatus + 2);
   a.slip2 = c->dstats;
   a.feat = c->feat;
-  constexpr int per = DIM == 3 ? 4 : 16;
-  int blocks = (c->nmk + per - 1) / per;
-  hipLaunchKernelGGL((k_interp<DIM, C>), dim3(blocks), dim3(256), 0, c->stream, a);
+  return a;
+}
+
+template <class T>
+LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
+  using C = typename Store<T>::C;
+  LdsArgs<C> a;
+  a.g = make_mgeo(c);
+  a.P = make_pview(c);
+  a.D = c->D;
+  a.mstart = c->mstart;
+  a.mcount = c->mcount;
+  a.cap = c->box_cap;
+  a.ustar = (C*)c->ustar;
+  a.facc = (C*)c->facc;
+  a.vd = c->vd;
+  a.half_inv_rho = C(0.5 / c->cfg.rho0);
+  a.two_rho = C(2.0 * c->cfg.rho0);
+  a.F = (C*)c->mF;
+  a.dF = (C*)c->mdF;
+  a.first_pass = first;
+  a.mode = mode;
+  a.trunc = (unsigned long long*)(c->dstatus + 2);
+  a.slip2 = c->dstats;
+  a.feat = c->feat;
+  a.bmap = c->bmap + (size_t)c->fbuf * c->nwords;
+  a.nwx = (int)c->nwx;
+  a.geo = make_geo<C>(c);
+  a.slot = make_slots(c);
+  a.inv_s = inv_scale<T>(c);
+  return a;
+}
+
+// one lane per point of the largest particle (at most 16 waves)
+int lds_threads(const iblbm_ctx* c) {
+  int mx = 0;
+  for (int m : c->hcount) mx = m > mx ? m : mx;
+  int t = ((mx + 63) / 64) * 64;
+  return t < 64 ? 64 : (t > LDS_THREADS ? LDS_THREADS : t);
 }
 
 template <int DIM, class C>
-void run_spread(iblbm_ctx* c) {
+size_t lds_bytes(int cap, bool interp) {
+  return (size_t)DIM * cap * sizeof(C) + (interp ? ((cap + 31) / 32) * 4 : 0);
+}
+
+template <int DIM, class T>
+struct RunInterp {
+  template <int PAR, int FIRST>
+  static void go(iblbm_ctx* c, LdsArgs<typename Store<T>::C>& a, size_t bytes) {
+    auto k = k_interp_lds<DIM, T, PAR, FIRST>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k, dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
+  }
+  static void run(iblbm_ctx* c, int first, int mode, bool* done) {
+    using C = typename Store<T>::C;
+    *done = false;
+    size_t bytes = lds_bytes<DIM, C>(c->box_cap, true);
+    if (!c->ibm_lds || c->box_cap <= 0 || bytes > (size_t)c->lds_max) return;
+    auto a = make_lds_args<T>(c, first, mode);
+    bool build = c->band_pending;
+    if (build) {
+      if (c->parity == 0) go<0, 1>(c, a, bytes); else go<1, 1>(c, a, bytes);
+    } else {
+      go<0, 0>(c, a, bytes);
+    }
+    c->band_pending = false;
+    *done = true;
+  }
+};
+
+template <int DIM, class T>
+struct RunSpread {
+  static void run(iblbm_ctx* c, bool* done) {
+    using C = typename Store<T>::C;
+    *done = false;
+    size_t bytes = lds_bytes<DIM, C>(c->box_cap, false);
+    if (!c->ibm_lds || c->box_cap <= 0 || bytes > (size_t)c->lds_max) return;
+    auto a = make_lds_args<T>(c, 0, 0);
+    auto k = k_spread_lds<DIM, C>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k, dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
+    *done = true;
+  }
+};
+
+template <int DIM, class T>
+struct RunBandPrep {
+  static void run(iblbm_ctx* c) {
+    auto a = make_lds_args<T>(c, 0, 0);
+    int blocks = (int)std::min<long long>(4096, (c->nseg + 15) / 16);
+    if (blocks < 1) blocks = 1;
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_band_prep<DIM, T, 0>), dim3(blocks), dim3(256), 0, c->stream, a,
+                         c->seglist, c->segcount, (int)c->nsegx);
+    else
+      hipLaunchKernelGGL((k_band_prep<DIM, T, 1>), dim3(blocks), dim3(256), 0, c->stream, a,
+                         c->seglist, c->segcount, (int)c->nsegx);
+  }
+};
+
+template <int DIM, class C>
+void run_point_interp(iblbm_ctx* c, int first, int mode) {
+  constexpr int per = DIM == 3 ? 4 : 16;
+  int blocks = (c->nmk + per - 1) / per;
+  hipLaunchKernelGGL((k_interp<DIM, C>), dim3(blocks), dim3(256), 0, c->stream,
+                     make_interp_args<C>(c, first, mode));
+}
+
+template <int DIM, class C>
+void run_point_spread(iblbm_ctx* c) {
   SpreadArgs<C> a;
   a.g = make_mgeo(c);
   a.P = make_pview(c);
@@ -355,45 +810,64 @@ void run_spread(iblbm_ctx* c) {
 
 }  // namespace
 
-void ibm_clear_and_mark(iblbm_ctx* c) {
-  int b = c->segcur;
-  int* cnt_old = c->segcount + b;
-  int* cnt_new = c->segcount + (1 - b);
-  hipLaunchKernelGGL(k_clear, dim3(256), dim3(256), 0, c->stream, c->bflag, c->seglist, cnt_old,
-                     cnt_new);
-  if (c->np > 0) {
-    MarkArgs a;
-    a.g = make_mgeo(c);
-    a.P = make_pview(c);
-    a.D = c->D;
-    a.mstart = c->mstart;
-    a.mcount = c->mcount;
-    a.bflag = c->bflag;
-    a.seglist = c->seglist;
-    a.count_new = cnt_new;
-    a.nsegx = (int)c->nsegx;
-    if (c->dim == 2)
-      hipLaunchKernelGGL(k_mark<2>, dim3(c->np), dim3(256), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL(k_mark<3>, dim3(c->np), dim3(256), 0, c->stream, a);
+bool ibm_uses_lds(const iblbm_ctx* c) {
+  size_t cs = c->fp64 ? 8 : 4;
+  return c->ibm_lds && c->box_cap > 0 &&
+         (size_t)c->dim * c->box_cap * cs + ((c->box_cap + 31) / 32) * 4 <= (size_t)c->lds_max;
+}
+
+// Band of this step.  On the per-particle path the first interpolation pass builds it;
+// otherwise list the touched segments and compute u* there now.
+void ibm_band(iblbm_ctx* c) {
+  c->band_pending = true;
+  if (ibm_uses_lds(c) || c->np == 0) return;
+  hipLaunchKernelGGL(k_clear, dim3(256), dim3(256), 0, c->stream, c->bflag, c->seglist,
+                     c->segcount);
+  hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, c->stream, c->segcount);
+  MarkArgs a;
+  a.g = make_mgeo(c);
+  a.P = make_pview(c);
+  a.D = c->D;
+  a.mstart = c->mstart;
+  a.mcount = c->mcount;
+  a.bflag = c->bflag;
+  a.seglist = c->seglist;
+  a.count = c->segcount;
+  a.nsegx = (int)c->nsegx;
+  {
+    // box side <= floor(D) + 7 nodes, so <= side/16 + 2 segments per row
+    int side = (int)llround(pow((double)c->box_cap, 1.0 / c->dim)) + 3;
+    long long nbits = (long long)(side / SEG + 2) * (c->dim == 3 ? (long long)side * side : side);
+    a.words = (int)std::min<long long>((nbits + 31) / 32, 8192);
   }
-  c->segcur = 1 - b;
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_mark<2>, dim3(c->np), dim3(256), a.words * 4, c->stream, a);
+  else
+    hipLaunchKernelGGL(k_mark<3>, dim3(c->np), dim3(256), a.words * 4, c->stream, a);
+  dispatch<RunBandPrep>(c);
+  c->band_pending = false;
 }
 
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode) {
   if (c->nmk == 0) return;
+  bool done = false;
+  dispatch<RunInterp>(c, first_pass, mode, &done);
+  if (done) return;
   if (c->dim == 2) {
-    if (c->fp64) run_interp<2, double>(c, first_pass, mode); else run_interp<2, float>(c, first_pass, mode);
+    if (c->fp64) run_point_interp<2, double>(c, first_pass, mode); else run_point_interp<2, float>(c, first_pass, mode);
   } else {
-    if (c->fp64) run_interp<3, double>(c, first_pass, mode); else run_interp<3, float>(c, first_pass, mode);
+    if (c->fp64) run_point_interp<3, double>(c, first_pass, mode); else run_point_interp<3, float>(c, first_pass, mode);
   }
 }
 
 void ibm_spread(iblbm_ctx* c, int) {
   if (c->nmk == 0) return;
+  bool done = false;
+  dispatch<RunSpread>(c, &done);
+  if (done) return;
   if (c->dim == 2) {
-    if (c->fp64) run_spread<2, double>(c); else run_spread<2, float>(c);
+    if (c->fp64) run_point_spread<2, double>(c); else run_point_spread<2, float>(c);
   } else {
-    if (c->fp64) run_spread<3, double>(c); else run_spread<3, float>(c);
+    if (c->fp64) run_point_spread<3, double>(c); else run_point_spread<3, float>(c);
   }
 }

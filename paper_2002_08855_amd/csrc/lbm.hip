@@ -8,137 +8,24 @@
 // each thread reads and writes the same set of locations and the update is in place
 // and race free.  Links that leave through a wall bounce back half-way with the
 // moving-wall term 2 w_a rho0 (e_a . u_w)/c_s^2.
-#include "common.h"
+#include "pdf_access.h"
 
 namespace {
 
-template <int DIM, class C>
-struct NodeCtx {
-  int x, y, z;
-  int i;
-};
+using namespace pdf;
 
-// Neighbour along +d (d = +-e_a) of node (x,y,z) and whether the link leaves through a
-// wall (then 'face' is the first wall face crossed, in axis order).
-template <int DX, int DY, int DZ, class C>
-__device__ __forceinline__ int neighbour(const Geo<C>& g, int x, int y, int z, bool& wall,
-                                         int& face) {
-  int c[3] = {x + DX, y + DY, z + DZ};
-  const int d[3] = {DX, DY, DZ};
-  wall = false;
-  face = 0;
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-    if (d[a] == 0) continue;
-    bool lo = c[a] < 0, hi = c[a] >= g.n[a];
-    if (lo || hi) {
-      if (g.periodic[a]) {
-        c[a] = lo ? c[a] + g.n[a] : c[a] - g.n[a];
-      } else if (!wall) {
-        wall = true;
-        face = 2 * a + (hi ? 1 : 0);
-      }
-    }
-  }
-  return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
-}
-
-template <int DIM, class T, int PAR, int A>
-struct LoadDir {
-  using C = typename Store<T>::C;
-  using L = Lat<DIM>;
-  __device__ __forceinline__ static C run(T* const* slot, const Geo<C>& g, int x, int y, int z,
-                                          int i, C inv_s) {
-    if (PAR == 0) return Store<T>::load(slot[A - 1][i], inv_s);
-    bool wall;
-    int face;
-    int j = neighbour<-L::ex[A], -L::ey[A], -L::ez[A], C>(g, x, y, z, wall, face);
-    constexpr int O = opp_dir(A, L::H);
-    if (!wall) return Store<T>::load(slot[O - 1][j], inv_s);
-    return Store<T>::load(slot[A - 1][i], inv_s) + g.wt[A][face];
-  }
-};
-
-template <int DIM, class T, int PAR, int A>
-struct StoreDir {
-  using C = typename Store<T>::C;
-  using L = Lat<DIM>;
-  __device__ __forceinline__ static void run(T* const* slot, const Geo<C>& g, int x, int y, int z,
-                                             int i, C v, C inv_s) {
-    constexpr int O = opp_dir(A, L::H);
-    if (PAR == 0) {
-      slot[O - 1][i] = Store<T>::save(v, inv_s);
-      return;
-    }
-    bool wall;
-    int face;
-    int j = neighbour<L::ex[A], L::ey[A], L::ez[A], C>(g, x, y, z, wall, face);
-    if (!wall)
-      slot[A - 1][j] = Store<T>::save(v, inv_s);
-    else
-      slot[O - 1][i] = Store<T>::save(v - g.wt[A][face], inv_s);
-  }
-};
-
-template <int DIM, class T, int PAR, int A = 1>
-__device__ __forceinline__ void load_all(T* const* slot, const Geo<typename Store<T>::C>& g, int x,
-                                         int y, int z, int i, typename Store<T>::C inv_s,
-                                         typename Store<T>::C* f) {
-  if constexpr (A < Lat<DIM>::Q) {
-    f[A] = LoadDir<DIM, T, PAR, A>::run(slot, g, x, y, z, i, inv_s);
-    load_all<DIM, T, PAR, A + 1>(slot, g, x, y, z, i, inv_s, f);
-  }
-}
-
-template <int DIM, class T, int PAR, int A = 1>
-__device__ __forceinline__ void store_all(T* const* slot, const Geo<typename Store<T>::C>& g, int x,
-                                          int y, int z, int i, typename Store<T>::C inv_s,
-                                          const typename Store<T>::C* f) {
-  if constexpr (A < Lat<DIM>::Q) {
-    StoreDir<DIM, T, PAR, A>::run(slot, g, x, y, z, i, f[A], inv_s);
-    store_all<DIM, T, PAR, A + 1>(slot, g, x, y, z, i, inv_s, f);
-  }
-}
-
-// u* = sum_a e_a f_a / rho0 (Eq. 5) and S = sum_{a>=1} f_a
-template <int DIM, class C>
-__device__ __forceinline__ void moments(const C* f, C rho0, C& S, C* us) {
-  using L = Lat<DIM>;
-  C s = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-  for (int a = 1; a < L::Q; a++) {
-    s += f[a];
-    if (L::ex[a] != 0) jx += L::ex[a] * f[a];
-    if (L::ey[a] != 0) jy += L::ey[a] * f[a];
-    if (DIM == 3 && L::ez[a] != 0) jz += L::ez[a] * f[a];
-  }
-  C ir = C(1) / rho0;
-  S = s;
-  us[0] = jx * ir;
-  us[1] = jy * ir;
-  us[2] = DIM == 3 ? jz * ir : C(0);
-}
-
-struct SlotPtrs {
-  void* p[18];
-};
-
-template <int DIM, class T>
-__device__ __forceinline__ void slots_of(const SlotPtrs& sp, T** s) {
-#pragma unroll
-  for (int a = 0; a < Lat<DIM>::Q - 1; a++) s[a] = reinterpret_cast<T*>(sp.p[a]);
-}
 
 template <class C>
 struct K1Args {
   Geo<C> g;
   SlotPtrs slot;
-  const uint32_t* bflag;
+  const uint32_t* bmap;  // band bitmap of this step: force present at set nodes
+  uint32_t* bmap_next;   // next step's bitmap, cleared here
+  int nwx;               // 32-node words per row
   const C* facc;
   int vd;
   C omega, kforce, rho0, body[3];
   C inv_s;
-  int nsegx;
   int nbx, bx_shift, nblk, xcd_per;
 };
 
@@ -167,7 +54,9 @@ __global__ __launch_bounds__(BX) void k_collide_stream(K1Args<typename Store<T>:
         (S - a.rho0 * w0 * (us[0] * us[0] + us[1] * us[1] + us[2] * us[2]) * C(1.5));
   // IB force where the band flag is set, plus the uniform body force
   C ff[3] = {a.body[0], a.body[1], a.body[2]};
-  if (a.bflag[x / SEG + a.nsegx * row] != 0u) {
+  int wi = (x >> 5) + a.nwx * row;
+  if ((x & 31) == 0) a.bmap_next[wi] = 0u;
+  if ((a.bmap[wi] >> (x & 31)) & 1u) {
     const C* fa = a.facc + (size_t)i * a.vd;
     ff[0] += fa[0];
     ff[1] += fa[1];
@@ -197,63 +86,13 @@ __global__ __launch_bounds__(BX) void k_collide_stream(K1Args<typename Store<T>:
 }
 
 template <class C>
-struct K2Args {
-  Geo<C> g;
-  SlotPtrs slot;
-  const int* seglist;
-  const int* segcount;
-  C* ustar;
-  C* facc;
-  int vd, nsegx;
-  C inv_s;
-  int* status;
-};
-
-// Band pass: at the nodes of every flagged segment compute u* from the PDFs in the
-// current A-A layout, and clear the force accumulator.
-template <int DIM, class T, int PAR>
-__global__ __launch_bounds__(256) void k_band_prep(K2Args<typename Store<T>::C> a) {
-  using C = typename Store<T>::C;
-  using L = Lat<DIM>;
-  int count = *a.segcount;
-  int lane = threadIdx.x & (SEG - 1);
-  T* slot[L::Q - 1];
-  slots_of<DIM, T>(a.slot, slot);
-  int groups = gridDim.x * (blockDim.x / SEG);
-  bool bad = false;
-  for (int s = blockIdx.x * (blockDim.x / SEG) + threadIdx.x / SEG; s < count; s += groups) {
-    int seg = a.seglist[s];
-    int sx = seg % a.nsegx, row = seg / a.nsegx;
-    int x = sx * SEG + lane;
-    if (x >= a.g.n[0]) continue;
-    int y = row % a.g.n[1], z = row / a.g.n[1];
-    int i = x + a.g.n[0] * row;
-    C f[L::Q];
-    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
-    C S, us[3];
-    moments<DIM, C>(f, a.g.rho0, S, us);
-    C* u = a.ustar + (size_t)i * a.vd;
-    C* fa = a.facc + (size_t)i * a.vd;
-    u[0] = us[0];
-    u[1] = us[1];
-    fa[0] = 0;
-    fa[1] = 0;
-    if (DIM == 3) {
-      u[2] = us[2];
-      fa[2] = 0;
-    }
-    bad |= !(us[0] == us[0]) || !(us[1] == us[1]) || !(us[2] == us[2]);
-  }
-  if (bad) atomicOr(a.status, ST_NAN);
-}
-
-template <class C>
 struct GatherArgs {
   Geo<C> g;
   SlotPtrs slot;
-  const uint32_t* bflag;
+  const uint32_t* bmap;
+  int nwx;
   const C* facc;
-  int vd, nsegx;
+  int vd;
   C inv_s;
   double *p, *u, *force, *fout;
 };
@@ -282,7 +121,8 @@ __global__ void k_gather(GatherArgs<typename Store<T>::C> a) {
     if (a.u) a.u[(size_t)c * a.g.N + i] = double(us[c]);
     if (a.force)
       a.force[(size_t)c * a.g.N + i] =
-          a.bflag[x / SEG + a.nsegx * row] ? double(a.facc[(size_t)i * a.vd + c]) : 0.0;
+          ((a.bmap[(x >> 5) + a.nwx * row] >> (x & 31)) & 1u) ? double(a.facc[(size_t)i * a.vd + c])
+                                                              : 0.0;
   }
 }
 
@@ -388,64 +228,6 @@ __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>
     }
 }
 
-template <class C>
-Geo<C> make_geo(const iblbm_ctx* c) {
-  Geo<C> g;
-  for (int a = 0; a < 3; a++) {
-    g.n[a] = c->cfg.n[a];
-    g.periodic[a] = c->cfg.periodic[a];
-  }
-  g.N = c->N;
-  g.rho0 = C(c->cfg.rho0);
-  const int* ex = c->dim == 2 ? Lat<2>::ex : Lat<3>::ex;
-  const int* ey = c->dim == 2 ? Lat<2>::ey : Lat<3>::ey;
-  const int* ez = c->dim == 2 ? Lat<2>::ez : Lat<3>::ez;
-  const double* w = c->dim == 2 ? Lat<2>::w : Lat<3>::w;
-  for (int d = 0; d < 19; d++)
-    for (int fc = 0; fc < 6; fc++) {
-      double v = 0;
-      if (d < c->q) {
-        double eu = ex[d] * c->cfg.wall_u[fc][0] + ey[d] * c->cfg.wall_u[fc][1] +
-                    ez[d] * c->cfg.wall_u[fc][2];
-        v = 2.0 * w[d] * c->cfg.rho0 * eu * 3.0;
-      }
-      g.wt[d][fc] = C(v);
-    }
-  return g;
-}
-
-SlotPtrs make_slots(const iblbm_ctx* c) {
-  SlotPtrs s;
-  for (int a = 0; a < 18; a++)
-    s.p[a] = a < c->q - 1 ? (char*)c->f + (size_t)a * c->N * c->sbytes : nullptr;
-  return s;
-}
-
-template <class T>
-typename Store<T>::C inv_scale(const iblbm_ctx* c) {
-  return c->storage == IBLBM_F16 ? typename Store<T>::C(1.0 / c->cfg.f16_scale)
-                                 : typename Store<T>::C(1);
-}
-
-// dispatch over (dim, storage) to a functor templated on <DIM, T>
-template <template <int, class> class F, class... Args>
-void dispatch(iblbm_ctx* c, Args... args) {
-  if (c->dim == 2) {
-    switch (c->storage) {
-      case IBLBM_F64: F<2, double>::run(c, args...); break;
-      case IBLBM_F32: F<2, float>::run(c, args...); break;
-      case IBLBM_BF16: F<2, bf16s>::run(c, args...); break;
-      default: F<2, __half>::run(c, args...); break;
-    }
-  } else {
-    switch (c->storage) {
-      case IBLBM_F64: F<3, double>::run(c, args...); break;
-      case IBLBM_F32: F<3, float>::run(c, args...); break;
-      case IBLBM_BF16: F<3, bf16s>::run(c, args...); break;
-      default: F<3, __half>::run(c, args...); break;
-    }
-  }
-}
 
 template <int DIM, class T>
 struct RunCollide {
@@ -464,7 +246,9 @@ struct RunCollide {
     K1Args<C> a;
     a.g = make_geo<C>(c);
     a.slot = make_slots(c);
-    a.bflag = c->bflag;
+    a.bmap = c->bmap + (size_t)c->fbuf * c->nwords;
+    a.bmap_next = c->bmap + (size_t)(1 - c->fbuf) * c->nwords;
+    a.nwx = (int)c->nwx;
     a.facc = (const C*)c->facc;
     a.vd = c->vd;
     a.omega = C(1.0 / c->cfg.tau);
@@ -472,7 +256,6 @@ struct RunCollide {
     a.rho0 = C(c->cfg.rho0);
     for (int k = 0; k < 3; k++) a.body[k] = k < DIM ? C(c->cfg.body_force[k]) : C(0);
     a.inv_s = inv_scale<T>(c);
-    a.nsegx = (int)c->nsegx;
     int nx = c->cfg.n[0];
     if (nx % 256 == 0 || nx > 1024)
       go<256>(c, a);
@@ -484,41 +267,17 @@ struct RunCollide {
 };
 
 template <int DIM, class T>
-struct RunBand {
-  static void run(iblbm_ctx* c) {
-    using C = typename Store<T>::C;
-    K2Args<C> a;
-    a.g = make_geo<C>(c);
-    a.slot = make_slots(c);
-    a.seglist = c->seglist;
-    a.segcount = c->segcount;
-    a.ustar = (C*)c->ustar;
-    a.facc = (C*)c->facc;
-    a.vd = c->vd;
-    a.nsegx = (int)c->nsegx;
-    a.inv_s = inv_scale<T>(c);
-    a.status = c->dstatus;
-    long long maxseg = c->nseg;
-    int blocks = (int)std::min<long long>(4096, (maxseg + 15) / 16);
-    if (blocks < 1) blocks = 1;
-    if (c->parity == 0)
-      hipLaunchKernelGGL((k_band_prep<DIM, T, 0>), dim3(blocks), dim3(256), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((k_band_prep<DIM, T, 1>), dim3(blocks), dim3(256), 0, c->stream, a);
-  }
-};
-
-template <int DIM, class T>
 struct RunGather {
   static void run(iblbm_ctx* c, double* p, double* u, double* force, double* fout) {
     using C = typename Store<T>::C;
     GatherArgs<C> a;
     a.g = make_geo<C>(c);
     a.slot = make_slots(c);
-    a.bflag = c->bflag;
+    // the bitmap of the most recent step
+    a.bmap = c->bmap + (size_t)c->fbuf * c->nwords;
+    a.nwx = (int)c->nwx;
     a.facc = (const C*)c->facc;
     a.vd = c->vd;
-    a.nsegx = (int)c->nsegx;
     a.inv_s = inv_scale<T>(c);
     a.p = p;
     a.u = u;
@@ -574,7 +333,6 @@ void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L) {
 }
 
 void lbm_collide_stream(iblbm_ctx* c) { dispatch<RunCollide>(c); }
-void lbm_band_prep(iblbm_ctx* c) { dispatch<RunBand>(c); }
 void lbm_get_fields(iblbm_ctx* c, double* p, double* u, double* force) {
   dispatch<RunGather>(c, p, u, force, (double*)nullptr);
 }

@@ -34,9 +34,10 @@ __device__ __forceinline__ int cell_coord(double x, double invh, int nc) {
   return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
 }
 
-// Cell of every particle and a slot in it.  Lanes of a wavefront that fall into the
-// same cell take one atomic between them: ballot the lanes matching the leader's cell,
-// let the leader add the popcount, and rank the others by their position in the mask.
+// Cell of every particle and a slot in it.  Consecutive lanes of a wavefront whose
+// particles share a cell form a run: a ballot of run heads gives every lane its head
+// and the run length, the head takes one atomic for the whole run, and the others
+// rank themselves by their distance from the head.
 __global__ void k_cells(PartArgs a) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool act = p < a.np;
@@ -47,23 +48,27 @@ __global__ void k_cells(PartArgs a) {
     for (int d = 0; d < 3; d++) a.cell_of[3 * p + d] = c[d];
     id = c[0] + (long long)a.nc[0] * (c[1] + (long long)a.nc[1] * c[2]);
   }
-  unsigned long long pending = __ballot(act);
   int lane = threadIdx.x & 63;
-  while (pending) {
-    int leader = __ffsll((long long)pending) - 1;
-    long long lid = __shfl(id, leader, 64);
-    unsigned long long same = __ballot(act && id == lid) & pending;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&a.cell_count[lid], __popcll(same));
-    base = __shfl(base, leader, 64);
-    if ((same >> lane) & 1ull) {
-      int rank = base + __popcll(same & ((1ull << lane) - 1ull));
-      if (rank < CELL_CAP)
-        a.cell_items[lid * CELL_CAP + rank] = p;
-      else
-        atomicOr(a.status, ST_CELL_OVERFLOW);
-    }
-    pending &= ~same;
+  long long prev = __shfl(id, lane > 0 ? lane - 1 : 0, 64);
+  bool head = act && (lane == 0 || prev != id);
+  unsigned long long heads = __ballot(head);
+  unsigned long long actm = __ballot(act);
+  unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  unsigned long long below = heads & upto;
+  int h = below ? 63 - __clzll(below) : 0;
+  int base = 0;
+  if (head) {
+    unsigned long long above = heads & ~upto;
+    int next = above ? __ffsll((long long)above) - 1 : __popcll(actm);
+    base = atomicAdd(&a.cell_count[id], next - lane);
+  }
+  base = __shfl(base, h, 64);
+  if (act) {
+    int rank = base + (lane - h);
+    if (rank < CELL_CAP)
+      a.cell_items[id * CELL_CAP + rank] = p;
+    else
+      atomicOr(a.status, ST_CELL_OVERFLOW);
   }
 }
 
@@ -78,52 +83,85 @@ __device__ double pair_mag(double d, double D, double zeta, double c, double eps
 
 constexpr int MAXP = 32;
 
-// Partners of each particle from the 5^d cell block, the pair force on it summed in
-// ascending partner order (pairs first, then the wall images in face order), and its
-// partners j > i for the pair list.
-__global__ void k_pairs(PartArgs a) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.np) return;
-  int nb[MAXP];
-  int cnt = 0;
+// One wavefront per particle: lanes scan the 5^d cells around it, candidates are
+// compacted with ballots into LDS, then one lane sorts the partners, sums the pair
+// forces in ascending partner order (pairs first, then the wall images in face order)
+// and writes the partners j > i for the pair list.
+__global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
+  __shared__ int cand[4][MAXP];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int i = blockIdx.x * 4 + wv;
+  bool act = i < a.np;
+  int ncand = 0;
   bool over = false;
-  const double* Xi = a.X + 3 * i;
-  int ci[3] = {a.cell_of[3 * i], a.cell_of[3 * i + 1], a.cell_of[3 * i + 2]};
-  int lo[3], hi[3];
-  for (int d = 0; d < 3; d++) {
-    lo[d] = d < a.dim ? max(ci[d] - 2, 0) : 0;
-    hi[d] = d < a.dim ? min(ci[d] + 2, a.nc[d] - 1) : 0;
-  }
-  for (int cz = lo[2]; cz <= hi[2]; cz++)
-    for (int cy = lo[1]; cy <= hi[1]; cy++)
-      for (int cx = lo[0]; cx <= hi[0]; cx++) {
-        long long id = cx + (long long)a.nc[0] * (cy + (long long)a.nc[1] * cz);
-        int m = min(a.cell_count[id], CELL_CAP);
-        for (int s = 0; s < m; s++) {
-          int j = a.cell_items[id * CELL_CAP + s];
-          if (j == i) continue;
-          const double* Xj = a.X + 3 * j;
-          double d2 = 0.0;
-          for (int d = 0; d < a.dim; d++) {
-            double dx = Xi[d] - Xj[d];
-            d2 = d2 + dx * dx;
-          }
-          double sr = 0.5 * (a.D[i] + a.D[j]) + a.zeta;
-          if (d2 < sr * sr) {
-            if (cnt < MAXP) {
-              // insertion into the ascending list
-              int k = cnt++;
-              while (k > 0 && nb[k - 1] > j) {
-                nb[k] = nb[k - 1];
-                k--;
-              }
-              nb[k] = j;
-            } else {
-              over = true;
+  if (act) {
+    const double* Xi = a.X + 3 * i;
+    int ci[3] = {a.cell_of[3 * i], a.cell_of[3 * i + 1], a.cell_of[3 * i + 2]};
+    int lo[3], w[3];
+    for (int d = 0; d < 3; d++) {
+      lo[d] = d < a.dim ? max(ci[d] - 2, 0) : 0;
+      int hi = d < a.dim ? min(ci[d] + 2, a.nc[d] - 1) : 0;
+      w[d] = hi - lo[d] + 1;
+    }
+    int nwin = w[0] * w[1] * w[2];
+    for (int t0 = 0; t0 < nwin; t0 += 64) {
+      int t = t0 + lane;
+      long long id = -1;
+      int m = 0;
+      if (t < nwin) {
+        int cx = lo[0] + t % w[0], cy = lo[1] + (t / w[0]) % w[1], cz = lo[2] + t / (w[0] * w[1]);
+        id = cx + (long long)a.nc[0] * (cy + (long long)a.nc[1] * cz);
+        m = min(a.cell_count[id], CELL_CAP);
+      }
+      for (int s = 0; s < CELL_CAP; s++) {
+        bool hit = false;
+        int j = -1;
+        if (s < m) {
+          j = a.cell_items[id * CELL_CAP + s];
+          if (j != i) {
+            const double* Xj = a.X + 3 * j;
+            double d2 = 0.0;
+            for (int d = 0; d < a.dim; d++) {
+              double dx = Xi[d] - Xj[d];
+              d2 = d2 + dx * dx;
             }
+            double sr = 0.5 * (a.D[i] + a.D[j]) + a.zeta;
+            hit = d2 < sr * sr;
           }
         }
+        unsigned long long mask = __ballot(hit);
+        if (mask == 0ull) {
+          if (!__ballot(s + 1 < m)) break;
+          continue;
+        }
+        int pos = ncand + __popcll(mask & ((1ull << lane) - 1ull));
+        if (hit) {
+          if (pos < MAXP)
+            cand[wv][pos] = j;
+          else
+            over = true;
+        }
+        ncand += __popcll(mask);
       }
+    }
+  }
+  __syncthreads();
+  if (!act || lane != 0) {
+    if (over) atomicOr(a.status, ST_PAIR_OVERFLOW);
+    return;
+  }
+  int cnt = min(ncand, MAXP);
+  int nb[MAXP];
+  for (int k = 0; k < cnt; k++) {
+    int j = cand[wv][k];
+    int q = k;
+    while (q > 0 && nb[q - 1] > j) {
+      nb[q] = nb[q - 1];
+      q--;
+    }
+    nb[q] = j;
+  }
+  const double* Xi = a.X + 3 * i;
   double F[3] = {0.0, 0.0, 0.0};
   int nup = 0;
   for (int k = 0; k < cnt; k++) {
@@ -160,7 +198,7 @@ __global__ void k_pairs(PartArgs a) {
   }
   for (int d = 0; d < 3; d++) a.Fc[3 * i + d] = F[d];
   a.pair_nup[i] = min(nup, PAIR_CAP);
-  if (over) atomicOr(a.status, ST_PAIR_OVERFLOW);
+  if (over || ncand > MAXP) atomicOr(a.status, ST_PAIR_OVERFLOW);
 }
 
 template <class C>
@@ -321,7 +359,7 @@ void part_cells_pairs(iblbm_ctx* c) {
   PartArgs a = make_pargs(c);
   int blocks = (c->np + 255) / 256;
   hipLaunchKernelGGL(k_cells, dim3(blocks), dim3(256), 0, c->stream, a);
-  hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_pairs, dim3((c->np + 3) / 4), dim3(256), 0, c->stream, a);
 }
 
 // loads and the Newton-Euler update (which also empties the cells used this step)
