@@ -155,6 +155,8 @@ struct iblbm_ctx {
   int* cell_of = nullptr;     // np x 3
   int* pair_up = nullptr;     // np x PAIR_CAP partners j > i, ascending
   int* pair_nup = nullptr;    // np
+  int* pair_all = nullptr;    // np x PAIR_CAP all partners, ascending
+  int* pair_nall = nullptr;   // np
   // status and statistics
   int* dstatus = nullptr;     // [0] flags, [1] truncated (int64 at [2..3]), ...
   double* dstats = nullptr;   // [0] slip sum of squares
@@ -166,6 +168,8 @@ struct iblbm_ctx {
   void* mlp_w = nullptr;      // packed weights for inference
   float* mlp_norm = nullptr;  // 26 floats
   float* feat = nullptr;      // nmk x 10 scratch
+  int* dcond = nullptr;       // device flag: run the MDF fallback of this step
+  const int* cond = nullptr;  // when set, IBM kernels run only if *cond != 0
   // timing
   bool timing = false;
   int timing_mask = 0;  // bit g: time kernel group g
@@ -206,6 +210,7 @@ void ibm_slip(iblbm_ctx* c);
 void part_cells_pairs(iblbm_ctx* c);
 void part_loads_newton(iblbm_ctx* c);
 void mlp_features(iblbm_ctx* c);
+void ibm_band_redo(iblbm_ctx* c);
 void mlp_infer(iblbm_ctx* c);
 
 // timing helpers (host.hip)

@@ -144,13 +144,14 @@ void marker_offsets(int dim, double R, int nl, std::vector<double>& r) {
 }
 
 void read_status(iblbm_ctx* c, int* flags) {
-  int st[4];
+  int st[8];
   HIPCHK(hipMemcpyAsync(st, c->dstatus, sizeof(st), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   *flags = st[0];
   unsigned long long t;
   memcpy(&t, st + 2, sizeof(t));
   c->truncated = (long long)t;
+  c->fallbacks = st[4];
 }
 
 void flush_timing(iblbm_ctx* c) {
@@ -292,6 +293,7 @@ iblbm_status iblbm_create(const iblbm_config* cfg, iblbm_ctx** out) {
     c->segcount = dzeros<int>(c, 1);
     c->dstatus = dzeros<int>(c, 8);
     c->dstats = dzeros<double>(c, 4);
+    c->dcond = dzeros<int>(c, 1);
     HIPCHK(hipStreamSynchronize(c->stream));
   } catch (Fail& f) {
     iblbm_destroy(c);
@@ -524,9 +526,13 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     if (c->cell_of) dfree(c, c->cell_of);
     if (c->pair_up) dfree(c, c->pair_up);
     if (c->pair_nup) dfree(c, c->pair_nup);
+    if (c->pair_all) dfree(c, c->pair_all);
+    if (c->pair_nall) dfree(c, c->pair_nall);
     c->cell_of = dzeros<int>(c, 3 * (size_t)np);
     c->pair_up = dzeros<int>(c, (size_t)np * PAIR_CAP);
     c->pair_nup = dzeros<int>(c, (size_t)np);
+    c->pair_all = dzeros<int>(c, (size_t)np * PAIR_CAP);
+    c->pair_nall = dzeros<int>(c, (size_t)np);
     // cells and pairs of the initial positions; then empty the cells again
     part_cells_pairs(c);
     part_zero_cells(c);

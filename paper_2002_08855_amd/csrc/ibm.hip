@@ -123,6 +123,7 @@ struct InterpArgs {
   unsigned long long* trunc;
   double* slip2;
   float* feat;  // nmk x 10
+  const int* cond;  // run only when *cond != 0 (if set)
 };
 
 // mode 0: a multi-direct-forcing pass (Eqs. 9-10): dF = 2 rho0 (U_b - D_I u), F += dF.
@@ -154,6 +155,7 @@ __device__ __forceinline__ void point_result(const InterpArgs<C>& a, int k, cons
 
 template <int DIM, class C>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
+  if (a.cond && *a.cond == 0) return;
   constexpr int G = DIM == 3 ? 64 : 16;
   int k = (blockIdx.x * blockDim.x + threadIdx.x) / G;
   int l = threadIdx.x & (G - 1);
@@ -192,11 +194,13 @@ struct SpreadArgs {
   const C* dF;  // nmk x 4
   C* facc;
   int vd;
+  const int* cond;
 };
 
 // Eq. 11 with Eq. 13: f(x) += dF_k Phi(x - X_k) drs ds_k, with float atomics.
 template <int DIM, class C>
 __global__ __launch_bounds__(256) void k_spread(SpreadArgs<C> a) {
+  if (a.cond && *a.cond == 0) return;
   constexpr int G = DIM == 3 ? 64 : 16;
   int k = (blockIdx.x * blockDim.x + threadIdx.x) / G;
   int l = threadIdx.x & (G - 1);
@@ -371,6 +375,7 @@ struct LdsArgs {
   float* feat;
   uint32_t* bmap;  // band bitmap of this step (bit per node, 32-node words per row)
   int nwx;         // words per row
+  const int* cond; // run only when *cond != 0 (if set)
   // PDF access for the first pass
   Geo<C> geo;
   SlotPtrs slot;
@@ -461,6 +466,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
   extern __shared__ double smem_d[];
+  if (a.cond && *a.cond == 0) return;
   C* ub = reinterpret_cast<C*>(smem_d);
   uint32_t* bits = reinterpret_cast<uint32_t*>(ub + DIM * a.cap);
   int p = blockIdx.x;
@@ -572,6 +578,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   extern __shared__ double smem_d[];
+  if (a.cond && *a.cond == 0) return;
   C* box = reinterpret_cast<C*>(smem_d);
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
@@ -618,6 +625,7 @@ __global__ __launch_bounds__(256) void k_band_prep(LdsArgs<typename Store<T>::C>
                                                     const int* seglist, const int* count, int nsegx) {
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
+  if (a.cond && *a.cond == 0) return;
   int n = *count;
   int lane = threadIdx.x & (SEG - 1);
   T* slot[L::Q - 1];
@@ -685,6 +693,7 @@ InterpArgs<C> make_interp_args(iblbm_ctx* c, int first, int mode) {
   a.trunc = (unsigned long long*)(c->dstatus + 2);
   a.slip2 = c->dstats;
   a.feat = c->feat;
+  a.cond = c->cond;
   return a;
 }
 
@@ -712,6 +721,7 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.feat = c->feat;
   a.bmap = c->bmap + (size_t)c->fbuf * c->nwords;
   a.nwx = (int)c->nwx;
+  a.cond = c->cond;
   a.geo = make_geo<C>(c);
   a.slot = make_slots(c);
   a.inv_s = inv_scale<T>(c);
@@ -803,6 +813,7 @@ void run_point_spread(iblbm_ctx* c) {
   a.dF = (const C*)c->mdF;
   a.facc = (C*)c->facc;
   a.vd = c->vd;
+  a.cond = c->cond;
   constexpr int per = DIM == 3 ? 4 : 16;
   int blocks = (c->nmk + per - 1) / per;
   hipLaunchKernelGGL((k_spread<DIM, C>), dim3(blocks), dim3(256), 0, c->stream, a);
@@ -846,6 +857,16 @@ void ibm_band(iblbm_ctx* c) {
     hipLaunchKernelGGL(k_mark<3>, dim3(c->np), dim3(256), a.words * 4, c->stream, a);
   dispatch<RunBandPrep>(c);
   c->band_pending = false;
+}
+
+// Recompute u* and clear the force at the band before a forcing redo (the per-particle
+// path does it in its first interpolation pass).
+void ibm_band_redo(iblbm_ctx* c) {
+  if (ibm_uses_lds(c)) {
+    c->band_pending = true;
+    return;
+  }
+  dispatch<RunBandPrep>(c);
 }
 
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode) {

@@ -26,6 +26,7 @@ struct PartArgs {
   int* cell_items;
   int* cell_of;
   int *pair_up, *pair_nup;
+  int *pair_all, *pair_nall;
   int* status;
 };
 
@@ -164,6 +165,8 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
   const double* Xi = a.X + 3 * i;
   double F[3] = {0.0, 0.0, 0.0};
   int nup = 0;
+  for (int k = 0; k < cnt && k < PAIR_CAP; k++) a.pair_all[i * PAIR_CAP + k] = nb[k];
+  a.pair_nall[i] = min(cnt, PAIR_CAP);
   for (int k = 0; k < cnt; k++) {
     int j = nb[k];
     int pa = i < j ? i : j, pb = i < j ? j : i;
@@ -323,6 +326,8 @@ PartArgs make_pargs(iblbm_ctx* c) {
   a.cell_of = c->cell_of;
   a.pair_up = c->pair_up;
   a.pair_nup = c->pair_nup;
+  a.pair_all = c->pair_all;
+  a.pair_nall = c->pair_nall;
   a.status = c->dstatus;
   return a;
 }

@@ -1,0 +1,84 @@
+"""Reduced-precision PDF storage: PDFs kept as BF16 or FP16 deviations from the rest
+state (FP16 with a power-of-two scale), collision in FP32, particles and per-particle
+reductions in FP64.  The error against the FP64 oracle is stated per field; the bounds
+below are sanity bounds derived from the storage precision (BF16 keeps 8 significant
+bits, relative rounding 2^-9 ~ 2e-3 per stored value; FP16 keeps 11, ~5e-4), accumulated
+over the run, not targets."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_08855_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_08855_amd import binding
+    return binding
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _run_pair(storage, steps, n=(48, 48, 48), seed=12):
+    b = _gpu()
+    p = inputs.default_params(3, n, tau=0.7, storage="f64", mdf_iters=3, stats_every=1)
+    X = inputs.jittered_grid(seed=seed, nx=2, ny=2, pitch=22.0, origin=13.0, jitter=1.5, nz=2)
+    D = np.full(len(X), 12.0)
+    rho = np.full(len(X), 2.0)
+    o = oracle.Sim(p)
+    g = b.Sim(dict(p, storage=storage))
+    for s in (g, o):
+        s.add_particles(X, D, rho, n_markers=452)
+    g.step(steps)
+    o.step(steps)
+    pg, ug, fg = g.fields()
+    po, uo, fo = o.fields()
+    Pg, Po = g.particles(), o.particles()
+    err = {
+        "p": rel_l2(pg, po), "u": rel_l2(ug, uo), "force": rel_l2(fg, fo),
+        "U": rel_l2(Pg["U"], Po["U"]), "X_disp": rel_l2(Pg["X"] - X, Po["X"] - X),
+        "Omega": rel_l2(Pg["Omega"], Po["Omega"]),
+        "slip_gpu": g.stats()["slip_rms"], "slip_oracle": o.slip_rms(),
+    }
+    return err
+
+
+@pytest.mark.parametrize("storage,bound", [("f32", 1e-5), ("f16", 5e-3), ("bf16", 3e-2)])
+def test_storage_error_per_field(storage, bound):
+    """48^3 cavity, 8 spheres D=12 (452 points each, density ratio 2), 100 steps."""
+    err = _run_pair(storage, 100)
+    print(storage, json.dumps(err))
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, f"precision_{storage}.json"), "w") as fh:
+        json.dump(err, fh)
+    for k in ("u", "force", "U", "X_disp"):
+        assert err[k] < bound, (k, err[k])
+    assert abs(err["slip_gpu"] - err["slip_oracle"]) < 0.1 * err["slip_oracle"] + 1e-9
+
+
+def test_f16_scale_power_of_two_roundtrip():
+    """FP16 storage keeps scale * f: a set/get round trip loses only FP16 rounding."""
+    b = _gpu()
+    p = inputs.default_params(3, (10, 9, 8), tau=0.8, storage="f16", f16_scale=1024.0)
+    g = b.Sim(p)
+    f0 = inputs.random_pdfs(7, 19, g.N, amplitude=1e-3)
+    g.set_pdfs(f0)
+    f1 = g.get_pdfs()
+    assert np.max(np.abs(f1 - f0)) <= 1e-3 * 2.0 ** -11 * 1.01
+    p2 = dict(p, storage="bf16")
+    g2 = b.Sim(p2)
+    g2.set_pdfs(f0)
+    f2 = g2.get_pdfs()
+    assert np.max(np.abs(f2 - f0) / np.maximum(np.abs(f0), 1e-30)) <= 2.0 ** -8 * 1.01
