@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
     unsigned long long m = __ballot(tr);
     if (l == 0 && m) {
       unsigned long long mine =
-          G == 64 ? m : (m >> (threadIdx.x & 63 & ~(G - 1))) & ((1ull << G) - 1);
+          G == 64 ? m : (m >> (threadIdx.x & 63 & ~(G - 1))) & ((1ull << (G & 63)) - 1);
       if (mine) atomicAdd(a.trunc, (unsigned long long)__popcll(mine));
     }
   }
@@ -376,6 +376,8 @@ struct LdsArgs {
   uint32_t* bmap;  // band bitmap of this step (bit per node, 32-node words per row)
   int nwx;         // words per row
   const int* cond; // run only when *cond != 0 (if set)
+  int mcap;        // points of the largest particle
+  int hcap;        // support columns (x, y) of the largest particle's box
   // PDF access for the first pass
   Geo<C> geo;
   SlotPtrs slot;
@@ -468,31 +470,29 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
   C* ub = reinterpret_cast<C*>(smem_d);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(ub + DIM * a.cap);
+  // touched-node flags, one byte per box node: every writer stores 1, so concurrent
+  // plain stores need no atomics
+  uint8_t* flag = reinterpret_cast<uint8_t*>(ub + DIM * a.cap);
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
   if (b.n > a.cap) return;  // the host sizes cap for the largest particle
-  int nw = (b.n + 31) >> 5;
-  for (int t = threadIdx.x; t < nw; t += blockDim.x) bits[t] = 0u;
+  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
   __syncthreads();
   int m0 = a.mstart[p], mc = a.mcount[p];
-  // each lane owns points k = m0 + threadIdx.x, + blockDim.x, ...; keep the first two
-  // supports in registers across the phases (more points per lane are recomputed)
   for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
     double X[3], Ub[3];
     marker_pos_vel(a.P, k, X, Ub, DIM);
     Support<DIM, C> s;
     point_support<DIM, C>(a.g, b, X, s);
-    for_support<DIM, C>(s, b, a.g.width,
-                        [&](int loc, C) { atomicOr(&bits[loc >> 5], 1u << (loc & 31)); });
+    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C) { flag[loc] = 1; });
   }
   __syncthreads();
   // stage u (first pass: u* from the PDFs, Eq. 5; later: u* + f/(2 rho0), Eq. 7)
   T* slot[L::Q - 1];
   if (FIRST) slots_of<DIM, T>(a.slot, slot);
   for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
-    if (!((bits[t >> 5] >> (t & 31)) & 1u)) continue;
+    if (!flag[t]) continue;
     int x = b.lo[0] + t % b.B[0];
     int y = b.lo[1] + (t / b.B[0]) % b.B[1];
     int z = b.lo[2] + t / (b.B[0] * b.B[1]);
@@ -525,8 +525,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
       int w0 = (b.lo[0] >= 0 ? b.lo[0] : 0) >> 5;
       uint32_t m[3] = {0u, 0u, 0u};
       for (int xl = 0; xl < b.B[0]; xl++) {
-        int t = xl + b.B[0] * r;
-        if (!((bits[t >> 5] >> (t & 31)) & 1u)) continue;
+        if (!flag[xl + b.B[0] * r]) continue;
         int x = b.lo[0] + xl;
         int wi = (x >> 5) - w0;
         if (wi >= 0 && wi < 3) m[wi] |= 1u << (x & 31);
@@ -573,48 +572,259 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   if (a.first_pass && a.mode == 0 && ntr) atomicAdd(a.trunc, ntr);
 }
 
-// Spreading of one forcing pass (Eq. 11 with Eq. 13), one lane per point, through the
-// particle's LDS box; each touched node then reaches the global force once.
+// 1-D weights of a point's support (the factors of Eq. 12).  With f the offset of X
+// past its first support node (Peskin 4-point) or from its nearest node (Roma
+// 3-point) and s the one square root both kernels need, the weight of support node q
+// is (k0 + k1 f + k2 s) * scale with constants that depend on q alone; this equals the
+// kernel evaluated at the node.
+template <class C>
+struct AxisForm {
+  C k0, k1, k2;
+};
+template <class C>
+__device__ __forceinline__ AxisForm<C> axis_form(int kind, int q) {
+  // Peskin: (3 - 2f - s, 3 - 2f + s, 1 + 2f + s, 1 + 2f - s) / 8
+  // Roma:   (2 - 3e - s, 2 + 2s, 2 + 3e - s, 0) / 6
+  const float P0[4] = {3, 3, 1, 1}, P1[4] = {-2, -2, 2, 2}, P2[4] = {-1, 1, 1, -1};
+  const float R0[4] = {2, 2, 2, 0}, R1[4] = {-3, 0, 3, 0}, R2[4] = {-1, 2, -1, 0};
+  AxisForm<C> r;
+  r.k0 = C(kind == 0 ? P0[q] : R0[q]);
+  r.k1 = C(kind == 0 ? P1[q] : R1[q]);
+  r.k2 = C(kind == 0 ? P2[q] : R2[q]);
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C axis_scale(int kind) {
+  return kind == 0 ? C(0.125) : C(1) / C(6);
+}
+// first support node of X along one axis, with f and s as above
+template <class C>
+__device__ __forceinline__ int axis_fs(int kind, double X, C& f, C& s) {
+  if (kind == 0) {
+    double fl = floor(X);
+    f = C(X - fl);
+    s = sqrt(C(1) + C(4) * f - C(4) * f * f);
+    return int(fl) - 1;
+  }
+  double cn = floor(X + 0.5);
+  f = C(X - cn);
+  s = sqrt(C(1) - C(3) * f * f);
+  return int(cn) - 1;
+}
+
+// LDS layout of the per-particle spreading kernel (the host sizes the dynamic LDS with
+// the same function):
+//   R0: C box[DIM][cap] node accumulators; while the point lists are built it holds
+//       int head[hcap] (list head per support column) and int rk[mcap]
+//   C   pfs[6][mcap]  f and s (see axis_fs) per axis of each point
+//   C   pf[3][mcap]   point force times its weight drs*ds (Eq. 13)
+//   int pcl[mcap]     box-local index of the first support node (-1: the support
+//                     leaves the box)
+//   int nxt[mcap]     next point of the same support column (-1 ends)
+//   int rep[mcap]     list heads ordered by colour
+//   int off[17]       colour offsets into rep
+struct SpreadLayout {
+  size_t pfs, pf, pcl, nxt, rep, off, rk, total;
+};
+__host__ __device__ inline SpreadLayout spread_layout(int dim, size_t cs, int cap, int mcap,
+                                                      int hcap) {
+  SpreadLayout L;
+  size_t r0 = (size_t)dim * cap * cs, lists = ((size_t)hcap + mcap) * 4;
+  size_t o = r0 > lists ? r0 : lists;
+  o = (o + 7) & ~(size_t)7;
+  L.rk = (size_t)hcap * 4;
+  L.pfs = o;
+  o += 6 * (size_t)mcap * cs;
+  L.pf = o;
+  o += 3 * (size_t)mcap * cs;
+  o = (o + 3) & ~(size_t)3;
+  L.pcl = o;
+  o += (size_t)mcap * 4;
+  L.nxt = o;
+  o += (size_t)mcap * 4;
+  L.rep = o;
+  o += (size_t)mcap * 4;
+  L.off = o;
+  o += 17 * 4;
+  L.total = o;
+  return L;
+}
+
+// Spreading of one forcing pass (Eq. 11 with Eq. 13) through the particle's LDS box.
+// The points whose supports start in the same (x, y) column form one list; lists are
+// coloured by that column modulo 4 per axis, so two lists of one colour touch disjoint
+// nodes.  Colour by colour, a group of 16 lanes, one per (x, y) of the support, takes a
+// list and walks it point by point and along z: each node is updated by one lane at a
+// time with plain LDS adds.  The box then reaches the global force once, one lane per
+// (node, component) so that neighbouring lanes hit neighbouring addresses.  A point
+// whose support leaves the box (not produced by the box construction) is spread
+// directly with global atomics.
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
-  C* box = reinterpret_cast<C*>(smem_d);
+  char* base = reinterpret_cast<char*>(smem_d);
+  const SpreadLayout Ly = spread_layout(DIM, sizeof(C), a.cap, a.mcap, a.hcap);
+  C* box = reinterpret_cast<C*>(base);
+  int* head = reinterpret_cast<int*>(base);
+  int* rk = reinterpret_cast<int*>(base + Ly.rk);
+  C* pfs = reinterpret_cast<C*>(base + Ly.pfs);
+  C* pf = reinterpret_cast<C*>(base + Ly.pf);
+  int* pcl = reinterpret_cast<int*>(base + Ly.pcl);
+  int* nxt = reinterpret_cast<int*>(base + Ly.nxt);
+  int* rep = reinterpret_cast<int*>(base + Ly.rep);
+  int* off = reinterpret_cast<int*>(base + Ly.off);
+  const int mcap = a.mcap;
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  if (b.n > a.cap) return;
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  const int kind = a.g.kind, width = a.g.width;
+  const int ncolumn = b.B[0] * b.B[1];
+  // the host sizes the arrays for the largest particle
+  if (b.n > a.cap || mc > mcap || ncolumn > a.hcap) return;
+  for (int t = threadIdx.x; t < ncolumn; t += blockDim.x) head[t] = -1;
+  for (int t = threadIdx.x; t < 17; t += blockDim.x) off[t] = 0;
+  __syncthreads();
+  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
+    int k = m0 + kl;
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    const C* d = a.dF + 4 * (size_t)k;
+    C dV = C(a.P.mdV[k]);
+    int l[3] = {0, 0, 0};
+    bool in = true;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ax++) {
+      C f, s;
+      l[ax] = axis_fs<C>(kind, X[ax], f, s) - b.lo[ax];
+      pfs[(2 * ax) * mcap + kl] = f;
+      pfs[(2 * ax + 1) * mcap + kl] = s;
+      in = in && l[ax] >= 0 && l[ax] + width <= b.B[ax];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; c++) pf[c * mcap + kl] = d[c] * dV;
+    pcl[kl] = in ? l[0] + b.B[0] * (l[1] + b.B[1] * l[2]) : -1;
+    nxt[kl] = in ? atomicExch(&head[l[0] + b.B[0] * l[1]], kl) : -1;
+  }
+  __syncthreads();
+  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
+    int v = pcl[kl];
+    int r = -1;
+    if (v >= 0) {
+      int col = v % ncolumn;
+      int lx = col % b.B[0], ly = col / b.B[0];
+      if (head[col] == kl) r = atomicAdd(&off[1 + (lx & 3) + 4 * (ly & 3)], 1);
+    }
+    rk[kl] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int v = threadIdx.x < 16 ? off[threadIdx.x + 1] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      int u = __shfl_up(v, o, 64);
+      if ((int)threadIdx.x >= o) v += u;
+    }
+    if (threadIdx.x < 16) off[threadIdx.x + 1] = v;
+  }
+  __syncthreads();
+  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
+    int r = rk[kl];
+    if (r < 0) continue;
+    int col = pcl[kl] % ncolumn;
+    rep[off[(col % b.B[0] & 3) + 4 * (col / b.B[0] & 3)] + r] = kl;
+  }
+  __syncthreads();
+  // the list arrays are done with: clear the accumulators
   for (int t = threadIdx.x; t < b.n; t += blockDim.x)
 #pragma unroll
     for (int c = 0; c < DIM; c++) box[c * a.cap + t] = C(0);
   __syncthreads();
-  int m0 = a.mstart[p], mc = a.mcount[p];
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    Support<DIM, C> s;
-    point_support<DIM, C>(a.g, b, X, s);
-    const C* d = a.dF + 4 * (size_t)k;
-    C dV = C(a.P.mdV[k]);
-    C Fk[3] = {d[0], d[1], DIM == 3 ? d[2] : C(0)};
-    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C w) {
-      C sw = w * dV;
+  {
+    const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
+    const int ix = lane & 3, iy = lane >> 2;
+    const bool active = ix < width && iy < width;
+    const AxisForm<C> fx = axis_form<C>(kind, ix), fy = axis_form<C>(kind, iy);
+    const C sc = axis_scale<C>(kind);
+    const int loff = ix + b.B[0] * iy, plane = b.B[0] * b.B[1];
+    for (int col = 0; col < 16; col++) {
+      const int j0 = off[col], j1 = off[col + 1];
+      if (j0 == j1) continue;  // the same for every lane
+      for (int j = j0 + grp; j < j1; j += ngrp) {
+        if (!active) continue;
+        for (int kl = rep[j]; kl >= 0; kl = nxt[kl]) {
+          C wx = (fx.k0 + fx.k1 * pfs[kl] + fx.k2 * pfs[mcap + kl]) * sc;
+          C wy = (fy.k0 + fy.k1 * pfs[2 * mcap + kl] + fy.k2 * pfs[3 * mcap + kl]) * sc;
+          // (phi_x phi_y) phi_z, the product order of Eq. 12
+          C wxy = wx * wy;
+          C F0 = pf[kl], F1 = pf[mcap + kl], F2 = DIM == 3 ? pf[2 * mcap + kl] : C(0);
+          int t = pcl[kl] + loff;
+          if (DIM == 3) {
+            C fz = pfs[4 * mcap + kl], sz = pfs[5 * mcap + kl];
 #pragma unroll
-      for (int c = 0; c < DIM; c++) atomicAdd(&box[c * a.cap + loc], Fk[c] * sw);
-    });
+            for (int iz = 0; iz < 4; iz++) {
+              if (iz >= width) break;
+              const AxisForm<C> fm = axis_form<C>(kind, iz);
+              C w = wxy * ((fm.k0 + fm.k1 * fz + fm.k2 * sz) * sc);
+              int u = t + iz * plane;
+              box[u] += F0 * w;
+              box[a.cap + u] += F1 * w;
+              box[2 * a.cap + u] += F2 * w;
+            }
+          } else {
+            box[t] += F0 * wxy;
+            box[a.cap + t] += F1 * wxy;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
+  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
+    if (pcl[kl] >= 0) continue;
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, m0 + kl, X, Ub, DIM);
+    C w[3][4] = {};
+    int g0[3] = {0, 0, 0};
+    const C sc = axis_scale<C>(kind);
+    for (int ax = 0; ax < DIM; ax++) {
+      C f, s;
+      g0[ax] = axis_fs<C>(kind, X[ax], f, s);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const AxisForm<C> fm = axis_form<C>(kind, q);
+        w[ax][q] = (fm.k0 + fm.k1 * f + fm.k2 * s) * sc;
+      }
+    }
+    const int wz = DIM == 3 ? width : 1;
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 4 : 1); iz++)
+#pragma unroll
+      for (int iy = 0; iy < 4; iy++)
+#pragma unroll
+        for (int ix = 0; ix < 4; ix++) {
+          int gx = g0[0] + ix, gy = g0[1] + iy, gz = g0[2] + iz;
+          if (iz >= wz || iy >= width || ix >= width || gx < 0 || gx >= a.g.n[0] || gy < 0 ||
+              gy >= a.g.n[1] || gz < 0 || gz >= a.g.n[2])
+            continue;
+          C wt = w[0][ix] * w[1][iy];
+          if (DIM == 3) wt *= w[2][iz];
+          C* f = a.facc + (size_t)(gx + a.g.n[0] * (gy + a.g.n[1] * gz)) * a.vd;
+          for (int c = 0; c < DIM; c++) unsafeAtomicAdd(f + c, pf[c * mcap + kl] * wt);
+        }
+  }
+  // flush: one lane per (node, component) of the box
+  const int nu = b.n * a.vd;
+  for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+    const int t = u / a.vd, c = u - t * a.vd;
+    if (c >= DIM) continue;
+    const C v = box[c * a.cap + t];
+    if (v == C(0)) continue;
     int x = b.lo[0] + t % b.B[0];
     int y = b.lo[1] + (t / b.B[0]) % b.B[1];
     int z = b.lo[2] + t / (b.B[0] * b.B[1]);
     if (x < 0 || x >= a.g.n[0] || y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
-    C* f = a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
-#pragma unroll
-    for (int c = 0; c < DIM; c++) {
-      C v = box[c * a.cap + t];
-      if (v != C(0)) unsafeAtomicAdd(f + c, v);
-    }
+    unsafeAtomicAdd(a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd + c, v);
   }
 }
 
@@ -697,6 +907,18 @@ InterpArgs<C> make_interp_args(iblbm_ctx* c, int first, int mode) {
   return a;
 }
 
+// points of the largest particle
+int max_points(const iblbm_ctx* c) {
+  int mx = 1;
+  for (int m : c->hcount) mx = m > mx ? m : mx;
+  return mx;
+}
+
+// side of the largest particle's box
+int box_side(const iblbm_ctx* c) {
+  return c->box_cap > 0 ? (int)llround(pow((double)c->box_cap, 1.0 / c->dim)) : 0;
+}
+
 template <class T>
 LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   using C = typename Store<T>::C;
@@ -722,6 +944,8 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.bmap = c->bmap + (size_t)c->fbuf * c->nwords;
   a.nwx = (int)c->nwx;
   a.cond = c->cond;
+  a.mcap = max_points(c);
+  a.hcap = box_side(c) * box_side(c);
   a.geo = make_geo<C>(c);
   a.slot = make_slots(c);
   a.inv_s = inv_scale<T>(c);
@@ -730,15 +954,16 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
 
 // one lane per point of the largest particle (at most 16 waves)
 int lds_threads(const iblbm_ctx* c) {
-  int mx = 0;
-  for (int m : c->hcount) mx = m > mx ? m : mx;
-  int t = ((mx + 63) / 64) * 64;
+  int t = ((max_points(c) + 63) / 64) * 64;
   return t < 64 ? 64 : (t > LDS_THREADS ? LDS_THREADS : t);
 }
 
-template <int DIM, class C>
-size_t lds_bytes(int cap, bool interp) {
-  return (size_t)DIM * cap * sizeof(C) + (interp ? ((cap + 31) / 32) * 4 : 0);
+// dynamic LDS of the per-particle kernels: interpolation stages DIM velocity
+// components and a flag byte per box node; spreading as laid out by spread_layout
+size_t lds_bytes(const iblbm_ctx* c, size_t cs, bool interp) {
+  if (interp) return (size_t)c->dim * c->box_cap * cs + (((size_t)c->box_cap + 3) & ~(size_t)3);
+  int side = box_side(c);
+  return spread_layout(c->dim, cs, c->box_cap, max_points(c), side * side).total;
 }
 
 template <int DIM, class T>
@@ -752,8 +977,8 @@ struct RunInterp {
   static void run(iblbm_ctx* c, int first, int mode, bool* done) {
     using C = typename Store<T>::C;
     *done = false;
-    size_t bytes = lds_bytes<DIM, C>(c->box_cap, true);
-    if (!c->ibm_lds || c->box_cap <= 0 || bytes > (size_t)c->lds_max) return;
+    size_t bytes = lds_bytes(c, sizeof(C), true);
+    if (!ibm_uses_lds(c)) return;
     auto a = make_lds_args<T>(c, first, mode);
     bool build = c->band_pending;
     if (build) {
@@ -771,8 +996,8 @@ struct RunSpread {
   static void run(iblbm_ctx* c, bool* done) {
     using C = typename Store<T>::C;
     *done = false;
-    size_t bytes = lds_bytes<DIM, C>(c->box_cap, false);
-    if (!c->ibm_lds || c->box_cap <= 0 || bytes > (size_t)c->lds_max) return;
+    size_t bytes = lds_bytes(c, sizeof(C), false);
+    if (!ibm_uses_lds(c)) return;
     auto a = make_lds_args<T>(c, 0, 0);
     auto k = k_spread_lds<DIM, C>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -823,8 +1048,8 @@ void run_point_spread(iblbm_ctx* c) {
 
 bool ibm_uses_lds(const iblbm_ctx* c) {
   size_t cs = c->fp64 ? 8 : 4;
-  return c->ibm_lds && c->box_cap > 0 &&
-         (size_t)c->dim * c->box_cap * cs + ((c->box_cap + 31) / 32) * 4 <= (size_t)c->lds_max;
+  return c->ibm_lds && c->box_cap > 0 && lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
+         lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
 
 // Band of this step.  On the per-particle path the first interpolation pass builds it;
