@@ -11,7 +11,6 @@ Prints one JSON line.  MLUPS = N_grid * steps / (1e6 * seconds) (the paper's Eq.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -23,15 +22,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 GROUPS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
-KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_band_prep/k_mark", "interp": "k_interp",
-               "spread": "k_spread", "interior": "k_interior", "particle": "k_pairs/k_loads_newton"}
-SOURCE_OF = {"collide": "lbm.hip", "band": "lbm.hip", "interior": "lbm.hip", "interp": "ibm.hip",
-             "spread": "ibm.hip", "particle": "particles.hip"}
-
-
-def _src_sha(name):
-    p = os.path.join(ROOT, "paper_2002_08855_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_band_prep", "interp": "k_interp_lds",
+               "spread": "k_spread_lds", "interior": "k_interior", "particle": "k_pairs"}
 
 
 def algorithmic_bytes(group, p, nmk, band_nodes):
@@ -56,7 +48,7 @@ def run(args):
     import numpy as np
     import torch
 
-    from paper_2002_08855_amd import binding, inputs
+    from paper_2002_08855_amd import binding, inputs, traffic
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs an MI355X GPU")
@@ -107,11 +99,11 @@ def run(args):
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": int(nbytes)}
-        prof = os.path.join(ROOT, "profiles", f"{KERNEL_NAME.get(dominant, dominant).split('/')[0]}"
-                            f"_{args.workload}_pmc.json")
+        kname = KERNEL_NAME.get(dominant, dominant)
+        prof = os.path.join(ROOT, "profiles", f"{kname}_{args.workload}_pmc.json")
         if os.path.exists(prof):
             d = json.load(open(prof))
-            if d.get("source_sha") == _src_sha(SOURCE_OF[dominant]):
+            if d.get("source_sha") == traffic.source_sha(kname):
                 roof["traffic"] = d.get("traffic_bytes_per_launch")
     # slip error of the step after the timed region
     sim.step(1)

@@ -45,7 +45,14 @@ __global__ __launch_bounds__(BX) void k_collide_stream(K1Args<typename Store<T>:
   T* slot[L::Q - 1];
   slots_of<DIM, T>(a.slot, slot);
   C f[L::Q];
-  load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+  // odd step: nodes away from every wall take the direct-offset path
+  const int sy = a.g.n[0], sz = a.g.n[0] * a.g.n[1];
+  const bool inner = PAR == 1 && x > 0 && x < a.g.n[0] - 1 && y > 0 && y < a.g.n[1] - 1 &&
+                     (DIM == 2 || (z > 0 && z < a.g.n[2] - 1));
+  if (inner)
+    load_odd_interior<DIM, T>(slot, i, sy, sz, a.inv_s, f);
+  else
+    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
   C S, us[3];
   moments<DIM, C>(f, a.rho0, S, us);
   const C w0 = C(L::w[0]);
@@ -82,7 +89,10 @@ __global__ __launch_bounds__(BX) void k_collide_stream(K1Args<typename Store<T>:
     post[d] = f[d] - a.omega * (f[d] - (ce + oe)) + (cf + of);
     post[o] = f[o] - a.omega * (f[o] - (ce - oe)) + (cf - of);
   }
-  store_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, post);
+  if (inner)
+    store_odd_interior<DIM, T>(slot, i, sy, sz, a.inv_s, post);
+  else
+    store_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, post);
 }
 
 template <class C>
