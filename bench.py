@@ -175,8 +175,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the multi-GPU slab decomposition is design only)"}))
+        print(json.dumps({"error": "the IB-LBM step runs on one GPU; --gpus above 1 is not "
+                                   "supported (the multi-GPU slab decomposition is not built)"}))
         sys.exit(2)
     out = run(args)
     print(json.dumps(out), flush=True)

@@ -377,7 +377,6 @@ struct LdsArgs {
   int nwx;         // words per row
   const int* cond; // run only when *cond != 0 (if set)
   int mcap;        // points of the largest particle
-  int hcap;        // support columns (x, y) of the largest particle's box
   // PDF access for the first pass
   Geo<C> geo;
   SlotPtrs slot;
@@ -612,181 +611,74 @@ __device__ __forceinline__ int axis_fs(int kind, double X, C& f, C& s) {
   return int(cn) - 1;
 }
 
-// LDS layout of the per-particle spreading kernel (the host sizes the dynamic LDS with
-// the same function):
-//   R0: C box[DIM][cap] node accumulators; while the point lists are built it holds
-//       int head[hcap] (list head per support column) and int rk[mcap]
-//   C   pfs[6][mcap]  f and s (see axis_fs) per axis of each point
-//   C   pf[3][mcap]   point force times its weight drs*ds (Eq. 13)
-//   int pcl[mcap]     box-local index of the first support node (-1: the support
-//                     leaves the box)
-//   int nxt[mcap]     next point of the same support column (-1 ends)
-//   int rep[mcap]     list heads ordered by colour
-//   int off[17]       colour offsets into rep
-struct SpreadLayout {
-  size_t pfs, pf, pcl, nxt, rep, off, rk, total;
+// Fixed-point accumulators of the spreading kernel: 32-bit for FP32 (and for the 16-bit
+// storage forms, which compute in FP32), 64-bit for FP64.  Integer additions are exact
+// and associative, so a node's sum does not depend on the order of its contributions,
+// and integer LDS atomics run at full rate on gfx950, where float LDS atomics do not.
+template <class C>
+struct Fixed;
+template <>
+struct Fixed<float> {
+  using U = unsigned int;
+  static constexpr int BITS = 30;  // |node sum| < 2^30
+  static constexpr int EMAX = 100; // largest scale exponent (keeps 2^-e a normal float)
+  __device__ static U quant(float x) { return (U)__float2int_rn(x); }
+  __device__ static float value(U u) { return float((int)u); }
 };
-__host__ __device__ inline SpreadLayout spread_layout(int dim, size_t cs, int cap, int mcap,
-                                                      int hcap) {
-  SpreadLayout L;
-  size_t r0 = (size_t)dim * cap * cs, lists = ((size_t)hcap + mcap) * 4;
-  size_t o = r0 > lists ? r0 : lists;
-  o = (o + 7) & ~(size_t)7;
-  L.rk = (size_t)hcap * 4;
-  L.pfs = o;
-  o += 6 * (size_t)mcap * cs;
-  L.pf = o;
-  o += 3 * (size_t)mcap * cs;
-  o = (o + 3) & ~(size_t)3;
-  L.pcl = o;
-  o += (size_t)mcap * 4;
-  L.nxt = o;
-  o += (size_t)mcap * 4;
-  L.rep = o;
-  o += (size_t)mcap * 4;
-  L.off = o;
-  o += 17 * 4;
-  L.total = o;
-  return L;
+template <>
+struct Fixed<double> {
+  using U = unsigned long long;
+  static constexpr int BITS = 62;
+  static constexpr int EMAX = 900;
+  __device__ static U quant(double x) { return (U)__double2ll_rn(x); }
+  __device__ static double value(U u) { return double((long long)u); }
+};
+
+// dynamic LDS of the spreading kernel: Fixed<C>::U acc[DIM][cap], then double red[16]
+__host__ __device__ inline size_t spread_acc_bytes(int dim, size_t cs, int cap) {
+  return ((size_t)dim * cap * (cs == 8 ? 8 : 4) + 7) & ~(size_t)7;
 }
 
-// Spreading of one forcing pass (Eq. 11 with Eq. 13) through the particle's LDS box.
-// The points whose supports start in the same (x, y) column form one list; lists are
-// coloured by that column modulo 4 per axis, so two lists of one colour touch disjoint
-// nodes.  Colour by colour, a group of 16 lanes, one per (x, y) of the support, takes a
-// list and walks it point by point and along z: each node is updated by one lane at a
-// time with plain LDS adds.  The box then reaches the global force once, one lane per
-// (node, component) so that neighbouring lanes hit neighbouring addresses.  A point
-// whose support leaves the box (not produced by the box construction) is spread
-// directly with global atomics.
+// Spreading of one forcing pass (Eq. 11 with Eq. 13) through the particle's LDS box,
+// one lane per point.  The box holds fixed-point sums: the scale 2^e is chosen per
+// particle so that the sum of max_c |F_c drs ds| over all points, times the largest
+// product of 1-D weights, stays below 2^BITS; no node sum can exceed it, so none
+// overflows.  Each touched node then reaches the global force once, one lane per
+// (node, component) so that neighbouring lanes hit neighbouring addresses.
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
+  using FX = Fixed<C>;
+  using U = typename FX::U;
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
-  char* base = reinterpret_cast<char*>(smem_d);
-  const SpreadLayout Ly = spread_layout(DIM, sizeof(C), a.cap, a.mcap, a.hcap);
-  C* box = reinterpret_cast<C*>(base);
-  int* head = reinterpret_cast<int*>(base);
-  int* rk = reinterpret_cast<int*>(base + Ly.rk);
-  C* pfs = reinterpret_cast<C*>(base + Ly.pfs);
-  C* pf = reinterpret_cast<C*>(base + Ly.pf);
-  int* pcl = reinterpret_cast<int*>(base + Ly.pcl);
-  int* nxt = reinterpret_cast<int*>(base + Ly.nxt);
-  int* rep = reinterpret_cast<int*>(base + Ly.rep);
-  int* off = reinterpret_cast<int*>(base + Ly.off);
-  const int mcap = a.mcap;
+  U* acc = reinterpret_cast<U*>(smem_d);
+  double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_d) +
+                                          spread_acc_bytes(DIM, sizeof(C), a.cap));
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
   int m0 = a.mstart[p], mc = a.mcount[p];
+  // the host sizes the box and the block for the largest particle
+  if (b.n > a.cap || mc > (int)blockDim.x) return;
   const int kind = a.g.kind, width = a.g.width;
-  const int ncolumn = b.B[0] * b.B[1];
-  // the host sizes the arrays for the largest particle
-  if (b.n > a.cap || mc > mcap || ncolumn > a.hcap) return;
-  for (int t = threadIdx.x; t < ncolumn; t += blockDim.x) head[t] = -1;
-  for (int t = threadIdx.x; t < 17; t += blockDim.x) off[t] = 0;
-  __syncthreads();
-  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
-    int k = m0 + kl;
+  for (int t = threadIdx.x; t < b.n; t += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < DIM; c++) acc[c * a.cap + t] = U(0);
+  // this lane's point: 1-D weights, first support node, force times drs*ds (Eq. 13)
+  const int kl = threadIdx.x;
+  const bool has = kl < mc;
+  C w[3][4] = {};
+  int g0[3] = {0, 0, 0};
+  C F[3] = {C(0), C(0), C(0)};
+  double mag = 0.0;
+  if (has) {
+    const int k = m0 + kl;
     double X[3], Ub[3];
     marker_pos_vel(a.P, k, X, Ub, DIM);
     const C* d = a.dF + 4 * (size_t)k;
-    C dV = C(a.P.mdV[k]);
-    int l[3] = {0, 0, 0};
-    bool in = true;
-#pragma unroll
-    for (int ax = 0; ax < DIM; ax++) {
-      C f, s;
-      l[ax] = axis_fs<C>(kind, X[ax], f, s) - b.lo[ax];
-      pfs[(2 * ax) * mcap + kl] = f;
-      pfs[(2 * ax + 1) * mcap + kl] = s;
-      in = in && l[ax] >= 0 && l[ax] + width <= b.B[ax];
-    }
-#pragma unroll
-    for (int c = 0; c < DIM; c++) pf[c * mcap + kl] = d[c] * dV;
-    pcl[kl] = in ? l[0] + b.B[0] * (l[1] + b.B[1] * l[2]) : -1;
-    nxt[kl] = in ? atomicExch(&head[l[0] + b.B[0] * l[1]], kl) : -1;
-  }
-  __syncthreads();
-  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
-    int v = pcl[kl];
-    int r = -1;
-    if (v >= 0) {
-      int col = v % ncolumn;
-      int lx = col % b.B[0], ly = col / b.B[0];
-      if (head[col] == kl) r = atomicAdd(&off[1 + (lx & 3) + 4 * (ly & 3)], 1);
-    }
-    rk[kl] = r;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    int v = threadIdx.x < 16 ? off[threadIdx.x + 1] : 0;
-    for (int o = 1; o < 16; o <<= 1) {
-      int u = __shfl_up(v, o, 64);
-      if ((int)threadIdx.x >= o) v += u;
-    }
-    if (threadIdx.x < 16) off[threadIdx.x + 1] = v;
-  }
-  __syncthreads();
-  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
-    int r = rk[kl];
-    if (r < 0) continue;
-    int col = pcl[kl] % ncolumn;
-    rep[off[(col % b.B[0] & 3) + 4 * (col / b.B[0] & 3)] + r] = kl;
-  }
-  __syncthreads();
-  // the list arrays are done with: clear the accumulators
-  for (int t = threadIdx.x; t < b.n; t += blockDim.x)
-#pragma unroll
-    for (int c = 0; c < DIM; c++) box[c * a.cap + t] = C(0);
-  __syncthreads();
-  {
-    const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
-    const int ix = lane & 3, iy = lane >> 2;
-    const bool active = ix < width && iy < width;
-    const AxisForm<C> fx = axis_form<C>(kind, ix), fy = axis_form<C>(kind, iy);
+    const C dV = C(a.P.mdV[k]);
     const C sc = axis_scale<C>(kind);
-    const int loff = ix + b.B[0] * iy, plane = b.B[0] * b.B[1];
-    for (int col = 0; col < 16; col++) {
-      const int j0 = off[col], j1 = off[col + 1];
-      if (j0 == j1) continue;  // the same for every lane
-      for (int j = j0 + grp; j < j1; j += ngrp) {
-        if (!active) continue;
-        for (int kl = rep[j]; kl >= 0; kl = nxt[kl]) {
-          C wx = (fx.k0 + fx.k1 * pfs[kl] + fx.k2 * pfs[mcap + kl]) * sc;
-          C wy = (fy.k0 + fy.k1 * pfs[2 * mcap + kl] + fy.k2 * pfs[3 * mcap + kl]) * sc;
-          // (phi_x phi_y) phi_z, the product order of Eq. 12
-          C wxy = wx * wy;
-          C F0 = pf[kl], F1 = pf[mcap + kl], F2 = DIM == 3 ? pf[2 * mcap + kl] : C(0);
-          int t = pcl[kl] + loff;
-          if (DIM == 3) {
-            C fz = pfs[4 * mcap + kl], sz = pfs[5 * mcap + kl];
 #pragma unroll
-            for (int iz = 0; iz < 4; iz++) {
-              if (iz >= width) break;
-              const AxisForm<C> fm = axis_form<C>(kind, iz);
-              C w = wxy * ((fm.k0 + fm.k1 * fz + fm.k2 * sz) * sc);
-              int u = t + iz * plane;
-              box[u] += F0 * w;
-              box[a.cap + u] += F1 * w;
-              box[2 * a.cap + u] += F2 * w;
-            }
-          } else {
-            box[t] += F0 * wxy;
-            box[a.cap + t] += F1 * wxy;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int kl = threadIdx.x; kl < mc; kl += blockDim.x) {
-    if (pcl[kl] >= 0) continue;
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, m0 + kl, X, Ub, DIM);
-    C w[3][4] = {};
-    int g0[3] = {0, 0, 0};
-    const C sc = axis_scale<C>(kind);
     for (int ax = 0; ax < DIM; ax++) {
       C f, s;
       g0[ax] = axis_fs<C>(kind, X[ax], f, s);
@@ -796,35 +688,62 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
         w[ax][q] = (fm.k0 + fm.k1 * f + fm.k2 * s) * sc;
       }
     }
-    const int wz = DIM == 3 ? width : 1;
+#pragma unroll
+    for (int c = 0; c < DIM; c++) {
+      F[c] = d[c] * dV;
+      mag = fmax(mag, fabs(double(F[c])));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mag += __shfl_xor(mag, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mag;
+  __syncthreads();
+  double bound = 0.0;
+  for (int v = 0; v < (int)(blockDim.x >> 6); v++) bound += red[v];
+  // largest 1-D weight: 1/2 (Peskin, at r = 0) or 2/3 (Roma); 1% margin for rounding
+  const double wmax = kind == 0 ? 0.5 : 2.0 / 3.0;
+  bound *= 1.01 * (DIM == 3 ? wmax * wmax * wmax : wmax * wmax);
+  int e = bound > 0.0 ? FX::BITS - 1 - ilogb(bound) : 0;
+  e = e > FX::EMAX ? FX::EMAX : e;
+  const C scale = C(ldexp(1.0, e)), inv = C(ldexp(1.0, -e));
+  if (has) {
 #pragma unroll
     for (int iz = 0; iz < (DIM == 3 ? 4 : 1); iz++)
 #pragma unroll
       for (int iy = 0; iy < 4; iy++)
 #pragma unroll
         for (int ix = 0; ix < 4; ix++) {
-          int gx = g0[0] + ix, gy = g0[1] + iy, gz = g0[2] + iz;
-          if (iz >= wz || iy >= width || ix >= width || gx < 0 || gx >= a.g.n[0] || gy < 0 ||
-              gy >= a.g.n[1] || gz < 0 || gz >= a.g.n[2])
-            continue;
-          C wt = w[0][ix] * w[1][iy];
-          if (DIM == 3) wt *= w[2][iz];
-          C* f = a.facc + (size_t)(gx + a.g.n[0] * (gy + a.g.n[1] * gz)) * a.vd;
-          for (int c = 0; c < DIM; c++) unsafeAtomicAdd(f + c, pf[c * mcap + kl] * wt);
+          if ((DIM == 3 && iz >= width) || iy >= width || ix >= width) continue;
+          const int gx = g0[0] + ix, gy = g0[1] + iy, gz = g0[2] + iz;
+          if (gx < 0 || gx >= a.g.n[0] || gy < 0 || gy >= a.g.n[1] || gz < 0 || gz >= a.g.n[2])
+            continue;  // outside the walls: skipped (counted by the interpolation)
+          // (phi_x phi_y) phi_z, the product order of Eq. 12
+          const C ww = DIM == 3 ? (w[0][ix] * w[1][iy]) * w[2][iz] : w[0][ix] * w[1][iy];
+          const int lx = gx - b.lo[0], ly = gy - b.lo[1], lz = gz - b.lo[2];
+          if (lx >= 0 && lx < b.B[0] && ly >= 0 && ly < b.B[1] && lz >= 0 && lz < b.B[2]) {
+            const int t = lx + b.B[0] * (ly + b.B[1] * lz);
+#pragma unroll
+            for (int c = 0; c < DIM; c++) atomicAdd(&acc[c * a.cap + t], FX::quant(F[c] * ww * scale));
+          } else {
+            // a support node outside the box (not produced by the box construction)
+            C* f = a.facc + (size_t)(gx + a.g.n[0] * (gy + a.g.n[1] * gz)) * a.vd;
+#pragma unroll
+            for (int c = 0; c < DIM; c++) unsafeAtomicAdd(f + c, F[c] * ww);
+          }
         }
   }
-  // flush: one lane per (node, component) of the box
+  __syncthreads();
   const int nu = b.n * a.vd;
   for (int u = threadIdx.x; u < nu; u += blockDim.x) {
     const int t = u / a.vd, c = u - t * a.vd;
     if (c >= DIM) continue;
-    const C v = box[c * a.cap + t];
-    if (v == C(0)) continue;
+    const U q = acc[c * a.cap + t];
+    if (q == U(0)) continue;
     int x = b.lo[0] + t % b.B[0];
     int y = b.lo[1] + (t / b.B[0]) % b.B[1];
     int z = b.lo[2] + t / (b.B[0] * b.B[1]);
     if (x < 0 || x >= a.g.n[0] || y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
-    unsafeAtomicAdd(a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd + c, v);
+    unsafeAtomicAdd(a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd + c,
+                    FX::value(q) * inv);
   }
 }
 
@@ -945,7 +864,6 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.nwx = (int)c->nwx;
   a.cond = c->cond;
   a.mcap = max_points(c);
-  a.hcap = box_side(c) * box_side(c);
   a.geo = make_geo<C>(c);
   a.slot = make_slots(c);
   a.inv_s = inv_scale<T>(c);
@@ -959,11 +877,11 @@ int lds_threads(const iblbm_ctx* c) {
 }
 
 // dynamic LDS of the per-particle kernels: interpolation stages DIM velocity
-// components and a flag byte per box node; spreading as laid out by spread_layout
+// components and a flag byte per box node; spreading keeps fixed-point sums per node
+// and component plus a small reduction area
 size_t lds_bytes(const iblbm_ctx* c, size_t cs, bool interp) {
   if (interp) return (size_t)c->dim * c->box_cap * cs + (((size_t)c->box_cap + 3) & ~(size_t)3);
-  int side = box_side(c);
-  return spread_layout(c->dim, cs, c->box_cap, max_points(c), side * side).total;
+  return spread_acc_bytes(c->dim, cs, c->box_cap) + 16 * sizeof(double);
 }
 
 template <int DIM, class T>
@@ -1048,7 +966,8 @@ void run_point_spread(iblbm_ctx* c) {
 
 bool ibm_uses_lds(const iblbm_ctx* c) {
   size_t cs = c->fp64 ? 8 : 4;
-  return c->ibm_lds && c->box_cap > 0 && lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
+  return c->ibm_lds && c->box_cap > 0 && max_points(c) <= LDS_THREADS &&
+         lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
          lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
 

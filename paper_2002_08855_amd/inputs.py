@@ -9,7 +9,7 @@ rounds), so placements are reproducible on any machine.
 
 The paper's workload is particles settling in a closed cavity (Sec. 6.2): a synthetic
 setup with no dataset.  The presets below carry the sizes of the five workloads the
-build is measured on; their derivation is described next to each.
+IB-LBM step is measured on; their derivation is described next to each.
 """
 from __future__ import annotations
 
