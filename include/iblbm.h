@@ -159,6 +159,10 @@ iblbm_status iblbm_set_timing(iblbm_ctx* ctx, int32_t mask);
 iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
 #define IBLBM_OPT_IBM_LDS 1 /* 1 (default): per-particle LDS interpolation/spreading kernels;
                                0: the point-wise kernels with global atomics */
+#define IBLBM_OPT_BAND_PASS 2 /* per-particle kernels only: 1 = u* at the band nodes (Eq. 5)
+                                 in a lattice-ordered pass before the forcing passes
+                                 (default in 3-D), 0 = inside the first interpolation
+                                 pass (default in 2-D); the results are identical */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
 /* Capture each step as a HIP graph and replay it (0 = plain launches). */
 iblbm_status iblbm_set_graph(iblbm_ctx* ctx, int32_t on);

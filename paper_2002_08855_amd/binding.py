@@ -297,6 +297,10 @@ class Sim:
     def set_ibm_lds(self, on=True):
         self.set_option(1, int(on))
 
+    def set_band_pass(self, on=True):
+        """band u* in its own lattice pass (True) or in the first interpolation (False)"""
+        self.set_option(2, int(on))
+
     def set_graph(self, on=True):
         self._check(lib().iblbm_set_graph(self.h, int(on)))
 

@@ -119,7 +119,6 @@ struct iblbm_ctx {
   uint32_t* bmap = nullptr;   // 2 x nwords band bitmaps (bit per node), one per step parity
   long long nwords = 0, nwx = 0;  // words per bitmap, 32-node words per row
   int fbuf = 0;               // bitmap of the most recent step
-  bool band_pending = false;  // the next interpolation pass builds the band
   uint32_t* bflag = nullptr;  // nseg segment flags (per-point fallback band)
   int* seglist = nullptr;     // flagged segments
   int* segcount = nullptr;    // number of listed segments
@@ -138,6 +137,9 @@ struct iblbm_ctx {
   int box_cap = 0;     // nodes in the largest per-particle support box
   int lds_max = 65536; // LDS bytes a workgroup may use on this device
   bool ibm_lds = true; // per-particle LDS kernels for interpolation and spreading
+  int band_pass = -1;   // band u* in its own pass (1) or in the first interpolation (0);
+                        // -1: by dimension
+  bool band_pending = false;  // the next interpolation pass builds the band
   // markers
   int nmk = 0, capm = 0;
   int* mown = nullptr;

@@ -173,9 +173,9 @@ void enqueue_step(iblbm_ctx* c) {
     tbegin(c, IBLBM_T_PARTICLE);
     part_cells_pairs(c);
     tend(c);
-    if (!ibm_uses_lds(c)) tbegin(c, IBLBM_T_BAND);
+    tbegin(c, IBLBM_T_BAND);
     ibm_band(c);
-    if (!ibm_uses_lds(c)) tend(c);
+    tend(c);
     if (c->cfg.forcing == IBLBM_FORCING_LEARNED && c->has_mlp) {
       mlp_step_forcing(c);
     } else {
@@ -496,12 +496,12 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     c->hX = allX;
     c->hD = allD;
     c->hcount.insert(c->hcount.end(), mcount.begin(), mcount.end());
-    // per-particle support box of the largest particle (4-point kernel: at most
-    // floor(D) + 5 nodes per axis)
+    // per-particle support box of the largest particle (at most floor(D + 2e-9) + 5
+    // nodes per axis, the 1e-9 widening of the box radius included)
     {
       double dmax = 0;
       for (double d : allD) dmax = std::max(dmax, d);
-      int B = (int)floor(dmax) + 5;
+      int B = (int)floor(dmax + 2e-9) + 5;
       c->box_cap = dim == 2 ? B * B : B * B * B;
     }
     // cell grid (Eqs. 49-50) and pair buffers
@@ -731,6 +731,11 @@ iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
   if (!c) return IBLBM_E_ARG;
   if (option == IBLBM_OPT_IBM_LDS) {
     c->ibm_lds = value != 0;
+    c->graph_dirty = true;
+    return IBLBM_OK;
+  }
+  if (option == IBLBM_OPT_BAND_PASS) {
+    c->band_pass = value != 0 ? 1 : 0;
     c->graph_dirty = true;
     return IBLBM_OK;
   }

@@ -310,10 +310,14 @@ struct PBox {
   int lo[3], B[3], n;
 };
 
+// The box of nodes that the supports of a particle's points can reach.  R is widened by
+// 1e-9 so that a point whose offset from the centre rounds to slightly more than R
+// still has its support inside; the box side is at most floor(D + 2e-9) + 5 nodes.
 template <int DIM>
 __device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, int kind) {
   PBox<DIM> b;
   b.n = 1;
+  R += 1e-9;
   for (int d = 0; d < 3; d++) {
     if (d < DIM) {
       int lo = kind == 0 ? int(floor(Xc[d] - R)) - 1 : int(floor(Xc[d] - R + 0.5)) - 1;
@@ -327,33 +331,6 @@ __device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, in
     b.n *= b.B[d];
   }
   return b;
-}
-
-// support node of lane l as a box-local index (or -1: outside the walls or the box)
-template <int DIM, class C>
-__device__ __forceinline__ int support_local(const MarkerGeo& g, const PBox<DIM>& b,
-                                             const double* X, int l, C& w, bool& trunc) {
-  int id[3] = {l & 3, (l >> 2) & 3, (l >> 4) & 3};
-  w = C(1);
-  trunc = false;
-  bool inside = true;
-  int loc[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < DIM; a++) {
-    if (id[a] >= g.width) inside = false;
-    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
-    int cc = lo + id[a];
-    w *= phi<C>(g.kind, C(double(cc) - X[a]));
-    if (cc < 0 || cc >= g.n[a]) trunc = true;
-    loc[a] = cc - b.lo[a];
-    if (loc[a] < 0 || loc[a] >= b.B[a]) inside = false;
-  }
-  if (!inside) {
-    trunc = false;
-    return -1;
-  }
-  if (trunc) return -1;
-  return loc[0] + b.B[0] * (loc[1] + b.B[1] * loc[2]);
 }
 
 template <class C>
@@ -384,192 +361,6 @@ struct LdsArgs {
 };
 
 constexpr int LDS_THREADS = 1024;
-
-// Support of one point seen by the lane that owns it: the first node, the 1-D weights
-// phi(x - X) per axis (Eq. 12: the 2-D/3-D kernel is their product), which nodes lie
-// inside the walls, and the offset of the first node in the particle's box.
-template <int DIM, class C>
-struct Support {
-  int lo[3];
-  C w[3][4];
-  bool ok[3][4];
-  int box0;  // box-local index of the first node
-  int ntr;   // nodes outside the walls
-};
-
-template <int DIM, class C>
-__device__ __forceinline__ void point_support(const MarkerGeo& g, const PBox<DIM>& b,
-                                              const double* X, Support<DIM, C>& s) {
-  s.ntr = 0;
-  int loc[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      s.w[a][q] = C(a < DIM && q < g.width ? 0 : (q == 0 ? 1 : 0));
-      s.ok[a][q] = a >= DIM ? q == 0 : false;
-    }
-    s.lo[a] = 0;
-    if (a >= DIM) continue;
-    int lo = g.kind == 0 ? int(floor(X[a])) - 1 : int(floor(X[a] + 0.5)) - 1;
-    s.lo[a] = lo;
-    loc[a] = lo - b.lo[a];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      if (q >= g.width) continue;
-      int cc = lo + q;
-      s.w[a][q] = phi<C>(g.kind, C(double(cc) - X[a]));
-      // inside the walls and inside the particle's box
-      s.ok[a][q] = cc >= 0 && cc < g.n[a] && loc[a] + q >= 0 && loc[a] + q < b.B[a];
-    }
-  }
-  s.box0 = loc[0] + b.B[0] * (loc[1] + b.B[1] * loc[2]);
-  int nin[3] = {0, 0, 0}, wdt[3] = {1, 1, 1};
-#pragma unroll
-  for (int a = 0; a < DIM; a++) {
-    wdt[a] = g.width;
-#pragma unroll
-    for (int q = 0; q < 4; q++) nin[a] += (q < g.width && s.ok[a][q]) ? 1 : 0;
-  }
-  if (DIM == 2) nin[2] = 1;
-  s.ntr = wdt[0] * wdt[1] * wdt[2] - nin[0] * nin[1] * nin[2];
-}
-
-// visit every support node inside the walls: fn(box-local index, weight)
-template <int DIM, class C, class Fn>
-__device__ __forceinline__ void for_support(const Support<DIM, C>& s, const PBox<DIM>& b, int width,
-                                            Fn fn) {
-  const int W2 = DIM == 3 ? 4 : 1;
-#pragma unroll
-  for (int iz = 0; iz < W2; iz++) {
-    if (DIM == 3 && (iz >= width || !s.ok[2][iz])) continue;
-#pragma unroll
-    for (int iy = 0; iy < 4; iy++) {
-      if (iy >= width || !s.ok[1][iy]) continue;
-      C wyz = s.w[1][iy] * (DIM == 3 ? s.w[2][iz] : C(1));
-      int row = s.box0 + b.B[0] * (iy + b.B[1] * iz);
-#pragma unroll
-      for (int ix = 0; ix < 4; ix++) {
-        if (ix >= width || !s.ok[0][ix]) continue;
-        // (phi_x phi_y) phi_z, the product order of Eq. 12
-        C w = DIM == 3 ? (s.w[0][ix] * s.w[1][iy]) * s.w[2][iz] : s.w[0][ix] * s.w[1][iy];
-        (void)wyz;
-        fn(row + ix, w);
-      }
-    }
-  }
-}
-
-// Interpolation (+ point force) for one forcing pass, one lane per point; FIRST also
-// computes u* at the touched nodes and builds the band.
-template <int DIM, class T, int PAR, int FIRST>
-__global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Store<T>::C> a) {
-  using C = typename Store<T>::C;
-  using L = Lat<DIM>;
-  extern __shared__ double smem_d[];
-  if (a.cond && *a.cond == 0) return;
-  C* ub = reinterpret_cast<C*>(smem_d);
-  // touched-node flags, one byte per box node: every writer stores 1, so concurrent
-  // plain stores need no atomics
-  uint8_t* flag = reinterpret_cast<uint8_t*>(ub + DIM * a.cap);
-  int p = blockIdx.x;
-  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
-  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
-  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
-  __syncthreads();
-  int m0 = a.mstart[p], mc = a.mcount[p];
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    Support<DIM, C> s;
-    point_support<DIM, C>(a.g, b, X, s);
-    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C) { flag[loc] = 1; });
-  }
-  __syncthreads();
-  // stage u (first pass: u* from the PDFs, Eq. 5; later: u* + f/(2 rho0), Eq. 7)
-  T* slot[L::Q - 1];
-  if (FIRST) slots_of<DIM, T>(a.slot, slot);
-  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
-    if (!flag[t]) continue;
-    int x = b.lo[0] + t % b.B[0];
-    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
-    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
-    int i = x + a.g.n[0] * (y + a.g.n[1] * z);
-    C* us = a.ustar + (size_t)i * a.vd;
-    if (FIRST) {
-      C f[L::Q];
-      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, i, a.inv_s, f);
-      C S, u[3];
-      moments<DIM, C>(f, a.geo.rho0, S, u);
-      C* fa = a.facc + (size_t)i * a.vd;
-#pragma unroll
-      for (int c = 0; c < DIM; c++) {
-        ub[c * a.cap + t] = u[c];
-        us[c] = u[c];
-        fa[c] = C(0);
-      }
-    } else {
-      const C* fa = a.facc + (size_t)i * a.vd;
-#pragma unroll
-      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = us[c] + fa[c] * a.half_inv_rho;
-    }
-  }
-  if (FIRST) {
-    // band bitmap: one atomic per (row, 32-node word) of the box
-    int rows = b.B[1] * b.B[2];
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-      int y = b.lo[1] + r % b.B[1], z = b.lo[2] + r / b.B[1];
-      if (y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
-      int w0 = (b.lo[0] >= 0 ? b.lo[0] : 0) >> 5;
-      uint32_t m[3] = {0u, 0u, 0u};
-      for (int xl = 0; xl < b.B[0]; xl++) {
-        if (!flag[xl + b.B[0] * r]) continue;
-        int x = b.lo[0] + xl;
-        int wi = (x >> 5) - w0;
-        if (wi >= 0 && wi < 3) m[wi] |= 1u << (x & 31);
-      }
-      uint32_t* row = a.bmap + (size_t)a.nwx * (y + a.g.n[1] * z);
-      for (int wi = 0; wi < 3; wi++)
-        if (m[wi]) atomicOr(row + w0 + wi, m[wi]);
-    }
-  }
-  __syncthreads();
-  // gather each support from LDS (Eq. 9 with Eq. 12) and form the point force (Eq. 10)
-  unsigned long long ntr = 0;
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    Support<DIM, C> s;
-    point_support<DIM, C>(a.g, b, X, s);
-    ntr += s.ntr;
-    C acc[3] = {0, 0, 0};
-    for_support<DIM, C>(s, b, a.g.width, [&](int loc, C w) {
-#pragma unroll
-      for (int c = 0; c < DIM; c++) acc[c] += w * ub[c * a.cap + loc];
-    });
-    if (a.mode == 0) {
-      C* F = a.F + 4 * (size_t)k;
-      C* dF = a.dF + 4 * (size_t)k;
-      for (int c = 0; c < DIM; c++) {
-        C d = a.two_rho * (C(Ub[c]) - acc[c]);
-        dF[c] = d;
-        F[c] = a.first_pass ? d : F[c] + d;
-      }
-    } else if (a.mode == 1) {
-      double s2 = 0;
-      for (int c = 0; c < DIM; c++) {
-        double e = Ub[c] - double(acc[c]);
-        s2 += e * e;
-      }
-      atomicAdd(a.slip2, s2);
-    } else {
-      for (int c = 0; c < 3; c++)
-        a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
-    }
-  }
-  if (a.first_pass && a.mode == 0 && ntr) atomicAdd(a.trunc, ntr);
-}
 
 // 1-D weights of a point's support (the factors of Eq. 12).  With f the offset of X
 // past its first support node (Peskin 4-point) or from its nearest node (Roma
@@ -609,6 +400,317 @@ __device__ __forceinline__ int axis_fs(int kind, double X, C& f, C& s) {
   f = C(X - cn);
   s = sqrt(C(1) - C(3) * f * f);
   return int(cn) - 1;
+}
+
+// the support of one point: per-axis weights and first node
+template <class C>
+struct PointWeights {
+  C w[3][4];
+  int g0[3];
+};
+template <int DIM, class C>
+__device__ __forceinline__ void point_weights(int kind, const double* X, PointWeights<C>& pw) {
+  const C sc = axis_scale<C>(kind);
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    pw.g0[ax] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) pw.w[ax][q] = C(ax < DIM ? 0 : (q == 0 ? 1 : 0));
+  }
+#pragma unroll
+  for (int ax = 0; ax < DIM; ax++) {
+    C f, s;
+    pw.g0[ax] = axis_fs<C>(kind, X[ax], f, s);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const AxisForm<C> fm = axis_form<C>(kind, q);
+      pw.w[ax][q] = (fm.k0 + fm.k1 * f + fm.k2 * s) * sc;
+    }
+  }
+}
+
+// Visit every support node inside the walls and the particle's box: fn(box-local index,
+// weight with the (phi_x phi_y) phi_z product order of Eq. 12).  Returns the number of
+// support nodes outside the walls.
+template <int DIM, class C, class Fn>
+__device__ __forceinline__ int visit_support(const MarkerGeo& g, const PBox<DIM>& b,
+                                             const PointWeights<C>& pw, Fn fn) {
+  bool ok[3][4];
+  int nin[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    if (ax < DIM) {
+      nin[ax] = 0;
+      lo[ax] = pw.g0[ax] - b.lo[ax];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int c = pw.g0[ax] + q;
+      const bool wall_in = ax >= DIM ? q == 0 : (q < g.width && c >= 0 && c < g.n[ax]);
+      if (ax < DIM) nin[ax] += wall_in ? 1 : 0;
+      ok[ax][q] = wall_in && (ax >= DIM || (lo[ax] + q >= 0 && lo[ax] + q < b.B[ax]));
+    }
+  }
+  const int base = lo[0] + b.B[0] * (lo[1] + b.B[1] * lo[2]);
+#pragma unroll
+  for (int iz = 0; iz < (DIM == 3 ? 4 : 1); iz++) {
+    if (!ok[2][iz]) continue;
+#pragma unroll
+    for (int iy = 0; iy < 4; iy++) {
+      if (!ok[1][iy]) continue;
+      const int row = base + b.B[0] * (iy + b.B[1] * iz);
+#pragma unroll
+      for (int ix = 0; ix < 4; ix++) {
+        if (!ok[0][ix]) continue;
+        const C ww = DIM == 3 ? (pw.w[0][ix] * pw.w[1][iy]) * pw.w[2][iz] : pw.w[0][ix] * pw.w[1][iy];
+        fn(row + ix, ww);
+      }
+    }
+  }
+  const int full = DIM == 3 ? g.width * g.width * g.width : g.width * g.width;
+  return full - nin[0] * nin[1] * nin[2];
+}
+
+// LDS layout of the per-particle interpolation kernel (the host sizes the dynamic LDS
+// with the same function): C ub[DIM][cap] staged velocities, uint8 flag[cap] touched
+// nodes, uint16 list[cap] the touched nodes in ascending order, int wcnt[17] per-wave
+// counts.
+struct InterpLayout {
+  size_t flag, list, wcnt, total;
+};
+__host__ __device__ inline InterpLayout interp_layout(int dim, size_t cs, int cap) {
+  InterpLayout L;
+  size_t o = ((size_t)dim * cap * cs + 7) & ~(size_t)7;
+  L.flag = o;
+  o += ((size_t)cap + 3) & ~(size_t)3;
+  L.list = o;
+  o += ((size_t)cap * 2 + 3) & ~(size_t)3;
+  L.wcnt = o;
+  o += 17 * 4;
+  L.total = o;
+  return L;
+}
+
+// Set the flagged nodes of a particle's box in the band bitmap, one lane per box row and
+// one atomic per (row, 32-node word).
+template <int DIM>
+__device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b,
+                                          const uint8_t* flag, uint32_t* bmap, int nwx) {
+  int rows = b.B[1] * b.B[2];
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    int y = b.lo[1] + r % b.B[1], z = b.lo[2] + r / b.B[1];
+    if (y < 0 || y >= g.n[1] || z < 0 || z >= g.n[2]) continue;
+    int w0 = (b.lo[0] >= 0 ? b.lo[0] : 0) >> 5;
+    uint32_t m[3] = {0u, 0u, 0u};
+    for (int xl = 0; xl < b.B[0]; xl++) {
+      if (!flag[xl + b.B[0] * r]) continue;
+      int x = b.lo[0] + xl;
+      int wi = (x >> 5) - w0;
+      if (wi >= 0 && wi < 3) m[wi] |= 1u << (x & 31);
+    }
+    uint32_t* row = bmap + (size_t)nwx * (y + g.n[1] * z);
+    for (int wi = 0; wi < 3; wi++)
+      if (m[wi]) atomicOr(row + w0 + wi, m[wi]);
+  }
+}
+
+// Band of this step for the per-particle path: flag the support nodes of every point of
+// the particle in LDS, then set them in the band bitmap with one atomic per (row,
+// 32-node word) of the particle's box.
+template <int DIM, class C>
+__global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
+  extern __shared__ double smem_d[];
+  uint8_t* flag = reinterpret_cast<uint8_t*>(smem_d);
+  int p = blockIdx.x;
+  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
+  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
+  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
+  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
+  __syncthreads();
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    PointWeights<C> pw;
+    point_weights<DIM, C>(a.g.kind, X, pw);
+    visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
+  }
+  __syncthreads();
+  band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
+}
+
+// u* at every band node (Eq. 5) and a cleared force there, one lane per lattice node in
+// row order so that the PDF slots are read with whole cache lines; nodes outside the
+// band only read their bitmap word.  Each lane takes NR rows (consecutive in y) and
+// issues the loads of all of them before using any.
+template <int DIM, class T, int PAR, int NR>
+__global__ __launch_bounds__(256) void k_band_ustar(LdsArgs<typename Store<T>::C> a, int nbx,
+                                                   int nrows) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  if (a.cond && *a.cond == 0) return;
+  const int bx = blockIdx.x % nbx, row0 = (blockIdx.x / nbx) * NR;
+  const int x = bx * 256 + threadIdx.x;
+  if (x >= a.g.n[0]) return;
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  C f[NR][L::Q];
+  bool on[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int row = row0 + r;
+    on[r] = row < nrows && ((a.bmap[(x >> 5) + a.nwx * row] >> (x & 31)) & 1u);
+    if (!on[r]) continue;
+    const int y = row % a.g.n[1], z = row / a.g.n[1];
+    const int i = x + a.g.n[0] * row;
+    // odd parity: nodes away from every wall take the direct-offset path
+    const bool inner = PAR == 1 && x > 0 && x < a.g.n[0] - 1 && y > 0 && y < a.g.n[1] - 1 &&
+                       (DIM == 2 || (z > 0 && z < a.g.n[2] - 1));
+    if (inner)
+      load_odd_interior<DIM, T>(slot, i, a.g.n[0], a.g.n[0] * a.g.n[1], a.inv_s, f[r]);
+    else
+      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, i, a.inv_s, f[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    if (!on[r]) continue;
+    C S, u[3];
+    moments<DIM, C>(f[r], a.geo.rho0, S, u);
+    const size_t i = (size_t)(x + a.g.n[0] * (row0 + r)) * a.vd;
+#pragma unroll
+    for (int c = 0; c < DIM; c++) {
+      a.ustar[i + c] = u[c];
+      a.facc[i + c] = C(0);
+    }
+  }
+}
+
+// Interpolation (+ point force) for one forcing pass through the particle's LDS box.
+// The touched nodes are flagged (one lane per point), listed in ascending order (ballot
+// compaction, so that neighbouring lanes stage neighbouring nodes), staged into LDS as
+// u = u* + f/(2 rho0) (Eq. 7), and gathered by one lane per point.  u* and the cleared
+// force come from the band pass, or, with FIRST, are made here from the PDFs of the
+// touched nodes, which also enter the band bitmap.
+template <int DIM, class T, int PAR, int FIRST>
+__global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  extern __shared__ double smem_d[];
+  if (a.cond && *a.cond == 0) return;
+  char* base = reinterpret_cast<char*>(smem_d);
+  const InterpLayout Ly = interp_layout(DIM, sizeof(C), a.cap);
+  C* ub = reinterpret_cast<C*>(base);
+  // touched-node flags, one byte per box node: every writer stores 1, so concurrent
+  // plain stores need no atomics
+  uint8_t* flag = reinterpret_cast<uint8_t*>(base + Ly.flag);
+  uint16_t* list = reinterpret_cast<uint16_t*>(base + Ly.list);
+  int* wcnt = reinterpret_cast<int*>(base + Ly.wcnt);
+  int p = blockIdx.x;
+  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
+  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
+  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
+  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
+  __syncthreads();
+  int m0 = a.mstart[p], mc = a.mcount[p];
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    PointWeights<C> pw;
+    point_weights<DIM, C>(a.g.kind, X, pw);
+    visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
+  }
+  __syncthreads();
+  // list the flagged nodes in ascending order: each wave scans one chunk of the box
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int chunk = ((b.n + nw - 1) / nw + 63) & ~63;
+  const int c0 = wid * chunk, c1 = c0 + chunk < b.n ? c0 + chunk : b.n;
+  int cnt = 0;
+  for (int t0 = c0; t0 < c1; t0 += 64) {
+    const int t = t0 + lane;
+    cnt += __popcll(__ballot(t < c1 && flag[t]));
+  }
+  if (lane == 0) wcnt[wid] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int v = 0; v < nw; v++) {
+      int n = wcnt[v];
+      wcnt[v] = s;
+      s += n;
+    }
+    wcnt[16] = s;
+  }
+  __syncthreads();
+  int pos = wcnt[wid];
+  for (int t0 = c0; t0 < c1; t0 += 64) {
+    const int t = t0 + lane;
+    const bool f = t < c1 && flag[t];
+    const unsigned long long m = __ballot(f);
+    if (f) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)t;
+    pos += __popcll(m);
+  }
+  __syncthreads();
+  const int ntouch = wcnt[16];
+  T* slot[L::Q - 1];
+  if (FIRST) slots_of<DIM, T>(a.slot, slot);
+  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
+    const int t = list[j];
+    int x = b.lo[0] + t % b.B[0];
+    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
+    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+    const int ii = x + a.g.n[0] * (y + a.g.n[1] * z);
+    const size_t i = (size_t)ii * a.vd;
+    if (FIRST) {
+      C f[L::Q];
+      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, ii, a.inv_s, f);
+      C S, u[3];
+      moments<DIM, C>(f, a.geo.rho0, S, u);
+#pragma unroll
+      for (int c = 0; c < DIM; c++) {
+        ub[c * a.cap + t] = u[c];
+        a.ustar[i + c] = u[c];
+        a.facc[i + c] = C(0);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = a.ustar[i + c] + a.facc[i + c] * a.half_inv_rho;
+    }
+  }
+  if (FIRST) band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
+  __syncthreads();
+  // gather each support from LDS (Eq. 9 with Eq. 12) and form the point force (Eq. 10)
+  unsigned long long ntr = 0;
+  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+    double X[3], Ub[3];
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    PointWeights<C> pw;
+    point_weights<DIM, C>(a.g.kind, X, pw);
+    C acc[3] = {0, 0, 0};
+    ntr += visit_support<DIM, C>(a.g, b, pw, [&](int loc, C w) {
+#pragma unroll
+      for (int c = 0; c < DIM; c++) acc[c] += w * ub[c * a.cap + loc];
+    });
+    if (a.mode == 0) {
+      C* F = a.F + 4 * (size_t)k;
+      C* dF = a.dF + 4 * (size_t)k;
+      for (int c = 0; c < DIM; c++) {
+        C d = a.two_rho * (C(Ub[c]) - acc[c]);
+        dF[c] = d;
+        F[c] = a.first_pass ? d : F[c] + d;
+      }
+    } else if (a.mode == 1) {
+      double s2 = 0;
+      for (int c = 0; c < DIM; c++) {
+        double e = Ub[c] - double(acc[c]);
+        s2 += e * e;
+      }
+      atomicAdd(a.slip2, s2);
+    } else {
+      for (int c = 0; c < 3; c++)
+        a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
+    }
+  }
+  if (a.first_pass && a.mode == 0 && ntr) atomicAdd(a.trunc, ntr);
 }
 
 // Fixed-point accumulators of the spreading kernel: 32-bit for FP32 (and for the 16-bit
@@ -880,32 +982,61 @@ int lds_threads(const iblbm_ctx* c) {
 // components and a flag byte per box node; spreading keeps fixed-point sums per node
 // and component plus a small reduction area
 size_t lds_bytes(const iblbm_ctx* c, size_t cs, bool interp) {
-  if (interp) return (size_t)c->dim * c->box_cap * cs + (((size_t)c->box_cap + 3) & ~(size_t)3);
+  if (interp) return interp_layout(c->dim, cs, c->box_cap).total;
   return spread_acc_bytes(c->dim, cs, c->box_cap) + 16 * sizeof(double);
+}
+
+// interpolation: one lane per point; in 3-D also enough lanes to stage the touched
+// nodes of a box (about an eighth of it) in a few rounds (2-D boxes are small, and
+// one-wave blocks keep more particles per compute unit)
+int interp_threads(const iblbm_ctx* c) {
+  long long m = std::max<long long>(max_points(c), c->dim == 3 ? c->box_cap / 8 : 0);
+  long long t = ((m + 63) / 64) * 64;
+  return (int)std::min<long long>(std::max<long long>(t, 64), LDS_THREADS);
 }
 
 template <int DIM, class T>
 struct RunInterp {
-  template <int PAR, int FIRST>
-  static void go(iblbm_ctx* c, LdsArgs<typename Store<T>::C>& a, size_t bytes) {
-    auto k = k_interp_lds<DIM, T, PAR, FIRST>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL(k, dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
-  }
   static void run(iblbm_ctx* c, int first, int mode, bool* done) {
     using C = typename Store<T>::C;
     *done = false;
     size_t bytes = lds_bytes(c, sizeof(C), true);
     if (!ibm_uses_lds(c)) return;
     auto a = make_lds_args<T>(c, first, mode);
-    bool build = c->band_pending;
-    if (build) {
+    if (c->band_pending) {
       if (c->parity == 0) go<0, 1>(c, a, bytes); else go<1, 1>(c, a, bytes);
     } else {
       go<0, 0>(c, a, bytes);
     }
     c->band_pending = false;
     *done = true;
+  }
+  template <int PAR, int FIRST>
+  static void go(iblbm_ctx* c, LdsArgs<typename Store<T>::C>& a, size_t bytes) {
+    auto k = k_interp_lds<DIM, T, PAR, FIRST>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL(k, dim3(c->np), dim3(interp_threads(c)), bytes, c->stream, a);
+  }
+};
+
+// band of the per-particle path: the bitmap (mark = true) and u* with a cleared force
+template <int DIM, class T>
+struct RunBandLds {
+  static void run(iblbm_ctx* c, bool mark) {
+    using C = typename Store<T>::C;
+    auto a = make_lds_args<T>(c, 0, 0);
+    if (mark) {
+      size_t bytes = ((size_t)c->box_cap + 3) & ~(size_t)3;
+      hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
+    }
+    constexpr int NR = DIM == 2 ? 4 : 2;
+    int nbx = (c->cfg.n[0] + 255) / 256;
+    int nrows = c->cfg.n[1] * c->cfg.n[2];
+    long long nblk = (long long)nbx * ((nrows + NR - 1) / NR);
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_band_ustar<DIM, T, 0, NR>), dim3((unsigned)nblk), dim3(256), 0, c->stream, a, nbx, nrows);
+    else
+      hipLaunchKernelGGL((k_band_ustar<DIM, T, 1, NR>), dim3((unsigned)nblk), dim3(256), 0, c->stream, a, nbx, nrows);
   }
 };
 
@@ -966,16 +1097,27 @@ void run_point_spread(iblbm_ctx* c) {
 
 bool ibm_uses_lds(const iblbm_ctx* c) {
   size_t cs = c->fp64 ? 8 : 4;
-  return c->ibm_lds && c->box_cap > 0 && max_points(c) <= LDS_THREADS &&
+  return c->ibm_lds && c->box_cap > 0 && c->box_cap <= 65536 && max_points(c) <= LDS_THREADS &&
          lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
          lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
 
 // Band of this step.  On the per-particle path the first interpolation pass builds it;
 // otherwise list the touched segments and compute u* there now.
+// band u* in its own pass (the default in 3-D, where the band covers a large part of the
+// lattice and overlapping particle boxes would read shared nodes repeatedly)
+static bool band_pass(const iblbm_ctx* c) { return c->band_pass < 0 ? c->dim == 3 : c->band_pass != 0; }
+
 void ibm_band(iblbm_ctx* c) {
-  c->band_pending = true;
-  if (ibm_uses_lds(c) || c->np == 0) return;
+  c->band_pending = false;
+  if (c->np == 0) return;
+  if (ibm_uses_lds(c)) {
+    if (band_pass(c))
+      dispatch<RunBandLds>(c, true);
+    else
+      c->band_pending = true;
+    return;
+  }
   hipLaunchKernelGGL(k_clear, dim3(256), dim3(256), 0, c->stream, c->bflag, c->seglist,
                      c->segcount);
   hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, c->stream, c->segcount);
@@ -1000,17 +1142,20 @@ void ibm_band(iblbm_ctx* c) {
   else
     hipLaunchKernelGGL(k_mark<3>, dim3(c->np), dim3(256), a.words * 4, c->stream, a);
   dispatch<RunBandPrep>(c);
-  c->band_pending = false;
 }
 
 // Recompute u* and clear the force at the band before a forcing redo (the per-particle
 // path does it in its first interpolation pass).
 void ibm_band_redo(iblbm_ctx* c) {
+  if (c->np == 0) return;
   if (ibm_uses_lds(c)) {
-    c->band_pending = true;
-    return;
+    if (band_pass(c))
+      dispatch<RunBandLds>(c, false);
+    else
+      c->band_pending = true;
+  } else {
+    dispatch<RunBandPrep>(c);
   }
-  dispatch<RunBandPrep>(c);
 }
 
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode) {

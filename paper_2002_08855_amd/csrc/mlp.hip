@@ -442,7 +442,6 @@ void mlp_step_forcing(iblbm_ctx* c) {
     ibm_interp(c, m == 0, 0);
     ibm_spread(c, 0);
   }
-  c->band_pending = false;
   c->cond = nullptr;
   tend(c);
 }
@@ -481,7 +480,6 @@ iblbm_status iblbm_capture_samples(iblbm_ctx* c, float* feat, float* target) {
     ibm_interp(c, m == 0, 0);
     ibm_spread(c, 0);
   }
-  c->band_pending = false;
   std::vector<char> mf((size_t)c->nmk * 4 * (c->fp64 ? 8 : 4));
   bool ok = hipMemcpyAsync(feat, c->feat, (size_t)c->nmk * 10 * 4, hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
             hipMemcpyAsync(mf.data(), c->mF, mf.size(), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&

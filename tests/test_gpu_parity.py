@@ -101,14 +101,16 @@ def _cfg1():
     return w["params"], w["particles"]
 
 
-@pytest.mark.parametrize("lds", [1, 0])
-def test_cavity128_f64_particles_100_steps(lds):
+@pytest.mark.parametrize("lds,band", [(1, None), (1, 1), (0, None)])
+def test_cavity128_f64_particles_100_steps(lds, band):
     """The 2-D FP64 workload (16 disks, MDF-3): fields and particle states after 100
-    steps within 1e-12 relative, with the per-particle LDS kernels and the point-wise
-    ones."""
+    steps within 1e-12 relative, with the per-particle LDS kernels (band u* inside the
+    first interpolation, the 2-D default, or in its own pass) and the point-wise ones."""
     p, parts = _cfg1()
     g, o = _pair(p)
     g.set_ibm_lds(lds)
+    if band is not None:
+        g.set_band_pass(band)
     for s in (g, o):
         s.add_particles(parts["center"], parts["diameter"], parts["density"],
                         n_markers=parts["n_markers"])
@@ -177,21 +179,26 @@ def test_pairs_cells_bit_exact(dim, n, count):
     assert np.array_equal(g.pairs(), o.pairs())
 
 
-@pytest.mark.parametrize("lds,storage,tol", [(1, "f32", 1e-5), (0, "f32", 1e-5),
-                                             (1, "f64", 1e-12)])
-def test_cavity3d_particles(lds, storage, tol):
+@pytest.mark.parametrize("lds,storage,tol,band", [(1, "f32", 1e-5, None), (1, "f32", 1e-5, 0),
+                                                  (0, "f32", 1e-5, None),
+                                                  (1, "f64", 1e-12, None), (1, "f64", 1e-12, 0)])
+def test_cavity3d_particles(lds, storage, tol, band):
     """A 3-D cavity with spheres (MDF-3, 4-point delta), touching the walls' stencil
-    margins: fields within the storage tolerance."""
+    margins: fields within the storage tolerance; per-particle kernels with the band u*
+    in its own pass (the 3-D default) or inside the first interpolation, and the
+    point-wise kernels."""
     n = (48, 44, 40)
     p = inputs.default_params(3, n, tau=0.7, storage=storage, mdf_iters=3)
     X = inputs.jittered_grid(seed=9, nx=2, ny=2, pitch=20.0, origin=12.0, jitter=2.0, nz=2)
     g, o = _pair(p)
     g.set_ibm_lds(lds)
+    if band is not None:
+        g.set_band_pass(band)
     for s in (g, o):
         s.add_particles(X, np.full(len(X), 10.0), np.full(len(X), 2.0), n_markers=314)
     g.step(30)
     o.step(30)
-    _compare_fields(g, o, tol, f"3D {storage} particles lds={lds}")
+    _compare_fields(g, o, tol, f"3D {storage} particles lds={lds} band={band}")
     pg, po = g.particles(), o.particles()
     assert rel_l2(pg["U"], po["U"]) < 10 * tol
     assert g.stats()["truncated"] == o.truncated()
