@@ -55,7 +55,7 @@ def run(args):
     torch.cuda.set_device(0)
     w = inputs.workload(args.workload)
     p = dict(w["params"])
-    p["stats_every"] = args.warmup + args.steps
+    p["stats_every"] = 0  # no slip statistic inside the timed region
     parts = w["particles"]
     sim = binding.Sim(p)
     if parts is not None:
@@ -105,7 +105,17 @@ def run(args):
             d = json.load(open(prof))
             if d.get("source_sha") == traffic.source_sha(kname):
                 roof["traffic"] = d.get("traffic_bytes_per_launch")
+    # the collide-stream kernel against the HBM roofline, from the breakdown pass
+    roof_collide = None
+    if "collide" in per_group:
+        nb_c = algorithmic_bytes("collide", p, nmk, band_nodes)
+        ms_c = st["time_ms"]["collide"] / max(1, st["launches"]["collide"])
+        ach_c = nb_c / (ms_c * 1e-3) / 1e9
+        roof_collide = {"kernel": "k_collide_stream", "bound": "hbm", "achieved": round(ach_c, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_c / HBM_PEAK_GBS, 4),
+                        "avg_launch_ms": round(ms_c, 5), "algorithmic_bytes_per_launch": int(nb_c)}
     # slip error of the step after the timed region
+    sim.set_stats_every(1)
     sim.step(1)
     slip = sim.stats()["slip_rms"]
     out = {
@@ -128,11 +138,110 @@ def run(args):
                    "parallelism": "1 GPU"},
         "slip_rms": slip,
         "roofline": roof,
+        "roofline_collide_stream": roof_collide,
         "kernel_ms_per_step": {g: round(v, 5) for g, v in per_group.items()},
     }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_forms:
+        out["forms"] = run_forms(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args)
     return out
+
+
+def _timed(sim, N, steps, warmup):
+    """MLUPS over `steps` after `warmup`, then the slip rms of one more step"""
+    import torch
+
+    sim.set_stats_every(0)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    sim.set_stats_every(1)
+    sim.step(1)
+    st = sim.stats()
+    return {"value": round(N * steps / (1e6 * secs), 1), "ms_per_step": round(1e3 * secs / steps, 4),
+            "steps": steps, "warmup": warmup, "slip_rms": st["slip_rms"], "fallbacks": st["fallbacks"]}
+
+
+def _sim(binding, p, parts):
+    sim = binding.Sim(p)
+    sim.add_particles(parts["center"], parts["diameter"], parts["density"],
+                      n_markers=parts["n_markers"])
+    return sim
+
+
+def run_forms(args):
+    """The two other forms of the step on their workloads: PDFs stored as BF16 (384^3,
+    25033 spheres, volume fraction 0.40) and learned forcing (256^3, 2347 spheres, 0.30)
+    against plain 5-pass multi-direct forcing on the same workload.  The network is
+    trained here, on the GPU, on (features, converged force) pairs captured from the
+    plain solver."""
+    import numpy as np
+    import torch
+
+    from paper_2002_08855_amd import binding, inputs
+
+    forms = {}
+    steps, warmup = args.form_steps, 3
+    try:
+        w = inputs.workload("cavity384_bf16")
+        p = dict(w["params"])
+        sim = _sim(binding, p, w["particles"])
+        r = _timed(sim, int(np.prod(p["n"])), steps, warmup)
+        r.update({"workload": "cavity384_bf16", "dtype": "bf16-storage/f32",
+                  "particles": len(w["particles"]["center"])})
+        forms["bf16_storage"] = r
+        del sim
+        torch.cuda.empty_cache()
+    except Exception as e:  # reported, not fatal for the headline line
+        forms["bf16_storage"] = {"error": repr(e)}
+    try:
+        w = inputs.workload("cavity256_learned")
+        parts = w["particles"]
+        N = int(np.prod(w["params"]["n"]))
+        base = dict(w["params"])
+        plain = dict(base, forcing=0)
+        # training data: features and converged MDF-5 forces of two plain steps
+        sim = _sim(binding, plain, parts)
+        sim.step(warmup)
+        feats, tgts = [], []
+        for _ in range(2):
+            f, t = sim.capture_samples()
+            feats.append(f)
+            tgts.append(t)
+            sim.step(1)
+        del sim
+        f = np.concatenate(feats)
+        t = np.concatenate(tgts)
+        norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+        xn = (f - norm[:10]) / norm[10:20]
+        tn = (t - norm[20:23]) / norm[23:26]
+        P0 = np.random.default_rng(1).normal(0, 0.1, binding.NPARAM)
+        t0 = time.perf_counter()
+        P, curve = binding.nn_train(xn, tn, P0, epochs=3, batch=8192, lr=2e-3, seed=1)
+        train_s = time.perf_counter() - t0
+        sim = _sim(binding, plain, parts)
+        rp = _timed(sim, N, steps, warmup)
+        del sim
+        sim = _sim(binding, base, parts)
+        sim.set_mlp(P, norm)
+        rl = _timed(sim, N, steps, warmup)
+        del sim
+        torch.cuda.empty_cache()
+        rl.update({"workload": "cavity256_learned", "dtype": "f32, MLP in bf16 on MFMA",
+                   "particles": len(parts["center"]), "correction_passes": 1,
+                   "train": {"samples": int(len(f)), "epochs": 3, "seconds": round(train_s, 2),
+                             "loss_first": float(curve[0]), "loss_last": float(curve[-1])},
+                   "plain_mdf5": rp})
+        forms["learned_forcing"] = rl
+    except Exception as e:
+        forms["learned_forcing"] = {"error": repr(e)}
+    return forms
 
 
 def cpu_baseline(w, args):
@@ -173,6 +282,9 @@ def main():
     ap.add_argument("--workload", default="cavity2048_f32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the BF16-storage and learned-forcing forms")
+    ap.add_argument("--form-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the IB-LBM step runs on one GPU; --gpus above 1 is not "

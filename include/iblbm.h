@@ -163,6 +163,7 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
                                  in a lattice-ordered pass before the forcing passes
                                  (default in 3-D), 0 = inside the first interpolation
                                  pass (default in 2-D); the results are identical */
+#define IBLBM_OPT_STATS_EVERY 3 /* replaces the configuration's stats_every (>= 0) */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
 /* Capture each step as a HIP graph and replay it (0 = plain launches). */
 iblbm_status iblbm_set_graph(iblbm_ctx* ctx, int32_t on);

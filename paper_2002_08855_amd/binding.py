@@ -297,6 +297,10 @@ class Sim:
     def set_ibm_lds(self, on=True):
         self.set_option(1, int(on))
 
+    def set_stats_every(self, n):
+        """compute the slip statistic every n steps (0: never)"""
+        self.set_option(3, int(n))
+
     def set_band_pass(self, on=True):
         """band u* in its own lattice pass (True) or in the first interpolation (False)"""
         self.set_option(2, int(on))

@@ -739,6 +739,12 @@ iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
     c->graph_dirty = true;
     return IBLBM_OK;
   }
+  if (option == IBLBM_OPT_STATS_EVERY) {
+    if (value < 0) return fail(c, IBLBM_E_ARG, "stats_every must be >= 0");
+    c->cfg.stats_every = value;
+    c->graph_dirty = true;
+    return IBLBM_OK;
+  }
   return fail(c, IBLBM_E_ARG, "unknown option");
 }
 
