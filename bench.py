@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 GROUPS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
-KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_band_prep", "interp": "k_interp_lds",
+KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_band_ustar", "interp": "k_interp_lds",
                "spread": "k_spread_lds", "interior": "k_interior", "particle": "k_pairs"}
 
 
@@ -36,9 +36,17 @@ def algorithmic_bytes(group, p, nmk, band_nodes):
     if group == "collide":
         # read + write of the q-1 live PDFs per node, force read on band nodes
         return 2 * (q - 1) * s * N + dim * cs * band_nodes
+    # u* at the band nodes from their PDFs, written with the cleared force
+    band = (q - 1) * s * band_nodes + 2 * dim * cs * band_nodes
+    if group == "band":
+        return band
     if group == "interp":
-        # u* and force at band nodes; per point its offset (FP64), owner, F update, dF
-        return 2 * dim * cs * band_nodes + nmk * (8 * dim + 4 + 3 * dim * cs)
+        # u* and force at band nodes; per point its offset (FP64), owner, F update, dF;
+        # in 2-D the first of the mdf_iters passes also makes the band u* (averaged)
+        b = 2 * dim * cs * band_nodes + nmk * (8 * dim + 4 + 3 * dim * cs)
+        if dim == 2:
+            b += band / max(1, p["mdf_iters"])
+        return b
     if group == "spread":
         return 2 * dim * cs * band_nodes + nmk * (8 * dim + 4 + 8 + dim * cs)
     return None

@@ -80,6 +80,9 @@ def workload(name: str) -> dict:
     cavity2048_f32    : 2-D 2048^2, FP32, tau 0.6, area fraction 0.40: 5340 disks D=20,
                         64 points, ratio 1.5, random sequential addition, 500 steps.
     cavity2048_free   : the same cavity without particles.
+    cavity8192_free   : 2-D 8192^2 FP32 cavity without particles (2.1 GB of PDFs, far
+                        beyond the last-level cache: the collide-stream kernel against HBM).
+    cavity256_free    : 3-D 256^3 FP32 cavity without particles.
     cavity256_f32     : 3-D 256^3 D3Q19, FP32, tau 0.7, volume fraction 0.20: 1565
                         spheres D=16, 804 points, ratio 2.0, 200 steps.
     cavity384_bf16/_f16: 3-D 384^3, volume fraction 0.40: 25033 spheres D=12, 452 points,
@@ -102,6 +105,12 @@ def workload(name: str) -> dict:
         parts = dict(center=X, diameter=np.full(len(X), 20.0), density=np.full(len(X), 1.5),
                      n_markers=64)
         return dict(params=p, particles=parts, steps=500)
+    if name == "cavity8192_free":
+        return dict(params=default_params(2, (8192, 8192), tau=0.6, storage="f32", mdf_iters=3),
+                    particles=None, steps=200)
+    if name == "cavity256_free":
+        return dict(params=default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=3),
+                    particles=None, steps=200)
     if name == "cavity256_f32":
         p = default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=3)
         X = rsa(seed=3, dim=3, n=(256, 256, 256), count=1565, diameter=16.0, gap=0.5,
