@@ -140,6 +140,7 @@ struct iblbm_ctx {
   int band_pass = -1;   // band u* in its own pass (1) or in the first interpolation (0);
                         // -1: by dimension
   bool band_pending = false;  // the next interpolation pass builds the band
+  bool ustar_valid = false;   // ustar holds u* of every node for the current PDFs
   // markers
   int nmk = 0, capm = 0;
   int* mown = nullptr;
@@ -207,7 +208,9 @@ void ibm_band(iblbm_ctx* c);
 bool ibm_uses_lds(const iblbm_ctx* c);
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode);
 void ibm_spread(iblbm_ctx* c, int use_set);
-void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L);
+void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L, bool from_ustar);
+void lbm_ustar_all(iblbm_ctx* c);
+bool ibm_ustar_lattice(const iblbm_ctx* c);
 void ibm_slip(iblbm_ctx* c);
 void part_cells_pairs(iblbm_ctx* c);
 void part_loads_newton(iblbm_ctx* c);

@@ -202,9 +202,18 @@ void enqueue_step(iblbm_ctx* c) {
   lbm_collide_stream(c);
   tend(c);
   c->parity ^= 1;
+  c->ustar_valid = false;
   if (parts) {
+    // u* of the new PDFs at every node for the interior momentum and the next step's
+    // forcing passes (per-particle path with the lattice-ordered u* pass)
+    const bool lat = ibm_ustar_lattice(c);
+    if (lat) {
+      tbegin(c, IBLBM_T_BAND);
+      lbm_ustar_all(c);
+      tend(c);
+    }
     tbegin(c, IBLBM_T_INTERIOR);
-    lbm_interior_momentum(c, c->Pin, c->Lin);
+    lbm_interior_momentum(c, c->Pin, c->Lin, lat);
     tend(c);
     tbegin(c, IBLBM_T_PARTICLE);
     part_loads_newton(c);
@@ -537,7 +546,7 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     part_cells_pairs(c);
     part_zero_cells(c);
     // interior fluid momentum of the new particles in the current fluid
-    lbm_interior_momentum(c, c->Pin, c->Lin);
+    lbm_interior_momentum(c, c->Pin, c->Lin, false);
     HIPCHK(hipMemcpyAsync(c->Pprev + o3, c->Pin + o3, 3 * n * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->Lprev + o3, c->Lin + o3, 3 * n * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipGetLastError());

@@ -515,11 +515,13 @@ __device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b
 }
 
 // Band of this step for the per-particle path: flag the support nodes of every point of
-// the particle in LDS, then set them in the band bitmap with one atomic per (row,
-// 32-node word) of the particle's box.
+// the particle in LDS, clear the force there, and set them in the band bitmap with one
+// atomic per (row, 32-node word) of the particle's box.  u* comes from the lattice pass
+// after the previous collision.
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
   extern __shared__ double smem_d[];
+  if (a.cond && *a.cond == 0) return;
   uint8_t* flag = reinterpret_cast<uint8_t*>(smem_d);
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
@@ -536,53 +538,16 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
     visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
   }
   __syncthreads();
+  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
+    if (!flag[t]) continue;
+    int x = b.lo[0] + t % b.B[0];
+    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
+    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+    C* fa = a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
+#pragma unroll
+    for (int c = 0; c < DIM; c++) fa[c] = C(0);
+  }
   band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
-}
-
-// u* at every band node (Eq. 5) and a cleared force there, one lane per lattice node in
-// row order so that the PDF slots are read with whole cache lines; nodes outside the
-// band only read their bitmap word.  Each lane takes NR rows (consecutive in y) and
-// issues the loads of all of them before using any.
-template <int DIM, class T, int PAR, int NR>
-__global__ __launch_bounds__(256) void k_band_ustar(LdsArgs<typename Store<T>::C> a, int nbx,
-                                                   int nrows) {
-  using C = typename Store<T>::C;
-  using L = Lat<DIM>;
-  if (a.cond && *a.cond == 0) return;
-  const int bx = blockIdx.x % nbx, row0 = (blockIdx.x / nbx) * NR;
-  const int x = bx * 256 + threadIdx.x;
-  if (x >= a.g.n[0]) return;
-  T* slot[L::Q - 1];
-  slots_of<DIM, T>(a.slot, slot);
-  C f[NR][L::Q];
-  bool on[NR];
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    const int row = row0 + r;
-    on[r] = row < nrows && ((a.bmap[(x >> 5) + a.nwx * row] >> (x & 31)) & 1u);
-    if (!on[r]) continue;
-    const int y = row % a.g.n[1], z = row / a.g.n[1];
-    const int i = x + a.g.n[0] * row;
-    // odd parity: nodes away from every wall take the direct-offset path
-    const bool inner = PAR == 1 && x > 0 && x < a.g.n[0] - 1 && y > 0 && y < a.g.n[1] - 1 &&
-                       (DIM == 2 || (z > 0 && z < a.g.n[2] - 1));
-    if (inner)
-      load_odd_interior<DIM, T>(slot, i, a.g.n[0], a.g.n[0] * a.g.n[1], a.inv_s, f[r]);
-    else
-      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, i, a.inv_s, f[r]);
-  }
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    if (!on[r]) continue;
-    C S, u[3];
-    moments<DIM, C>(f[r], a.geo.rho0, S, u);
-    const size_t i = (size_t)(x + a.g.n[0] * (row0 + r)) * a.vd;
-#pragma unroll
-    for (int c = 0; c < DIM; c++) {
-      a.ustar[i + c] = u[c];
-      a.facc[i + c] = C(0);
-    }
-  }
 }
 
 // Interpolation (+ point force) for one forcing pass through the particle's LDS box.
@@ -1019,24 +984,14 @@ struct RunInterp {
   }
 };
 
-// band of the per-particle path: the bitmap (mark = true) and u* with a cleared force
+// band of the per-particle path with the lattice-ordered u*: bitmap and cleared force
 template <int DIM, class T>
-struct RunBandLds {
-  static void run(iblbm_ctx* c, bool mark) {
+struct RunMarkLds {
+  static void run(iblbm_ctx* c) {
     using C = typename Store<T>::C;
     auto a = make_lds_args<T>(c, 0, 0);
-    if (mark) {
-      size_t bytes = ((size_t)c->box_cap + 3) & ~(size_t)3;
-      hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
-    }
-    constexpr int NR = DIM == 2 ? 4 : 2;
-    int nbx = (c->cfg.n[0] + 255) / 256;
-    int nrows = c->cfg.n[1] * c->cfg.n[2];
-    long long nblk = (long long)nbx * ((nrows + NR - 1) / NR);
-    if (c->parity == 0)
-      hipLaunchKernelGGL((k_band_ustar<DIM, T, 0, NR>), dim3((unsigned)nblk), dim3(256), 0, c->stream, a, nbx, nrows);
-    else
-      hipLaunchKernelGGL((k_band_ustar<DIM, T, 1, NR>), dim3((unsigned)nblk), dim3(256), 0, c->stream, a, nbx, nrows);
+    size_t bytes = ((size_t)c->box_cap + 3) & ~(size_t)3;
+    hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
   }
 };
 
@@ -1104,18 +1059,23 @@ bool ibm_uses_lds(const iblbm_ctx* c) {
 
 // Band of this step.  On the per-particle path the first interpolation pass builds it;
 // otherwise list the touched segments and compute u* there now.
-// band u* in its own pass (the default in 3-D, where the band covers a large part of the
-// lattice and overlapping particle boxes would read shared nodes repeatedly)
+// u* of every node from a lattice-ordered pass after the collision (the default in 3-D,
+// where the band covers a large part of the lattice and overlapping particle boxes would
+// read shared nodes repeatedly), or at the touched nodes inside the first interpolation
 static bool band_pass(const iblbm_ctx* c) { return c->band_pass < 0 ? c->dim == 3 : c->band_pass != 0; }
+
+bool ibm_ustar_lattice(const iblbm_ctx* c) { return c->np > 0 && ibm_uses_lds(c) && band_pass(c); }
 
 void ibm_band(iblbm_ctx* c) {
   c->band_pending = false;
   if (c->np == 0) return;
   if (ibm_uses_lds(c)) {
-    if (band_pass(c))
-      dispatch<RunBandLds>(c, true);
-    else
+    if (band_pass(c)) {
+      if (!c->ustar_valid) lbm_ustar_all(c);
+      dispatch<RunMarkLds>(c);
+    } else {
       c->band_pending = true;
+    }
     return;
   }
   hipLaunchKernelGGL(k_clear, dim3(256), dim3(256), 0, c->stream, c->bflag, c->seglist,
@@ -1150,7 +1110,7 @@ void ibm_band_redo(iblbm_ctx* c) {
   if (c->np == 0) return;
   if (ibm_uses_lds(c)) {
     if (band_pass(c))
-      dispatch<RunBandLds>(c, false);
+      dispatch<RunMarkLds>(c);  // clears the force again; u* is unchanged
     else
       c->band_pending = true;
   } else {

@@ -178,13 +178,43 @@ struct InteriorArgs {
   C inv_s;
   const double *X, *D;
   double *P, *L;
+  const C* ustar;  // u* of every node (FROMU), else computed from the PDFs
+  int vd;
 };
+
+// u* = sum_a e_a f_a / rho0 (Eq. 5) at every node, from the PDFs after streaming, in
+// row order (the A-A access of the step's parity).  The immersed-boundary passes of the
+// next step and the interior momentum of the particles read it instead of the PDFs.
+template <int DIM, class T, int PAR>
+__global__ __launch_bounds__(256) void k_ustar_all(InteriorArgs<typename Store<T>::C> a, int nbx) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  const int bx = blockIdx.x % nbx, row = blockIdx.x / nbx;
+  const int x = bx * 256 + threadIdx.x;
+  if (x >= a.g.n[0]) return;
+  const int y = row % a.g.n[1], z = row / a.g.n[1];
+  const int i = x + a.g.n[0] * row;
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  C f[L::Q];
+  const bool inner = PAR == 1 && x > 0 && x < a.g.n[0] - 1 && y > 0 && y < a.g.n[1] - 1 &&
+                     (DIM == 2 || (z > 0 && z < a.g.n[2] - 1));
+  if (inner)
+    load_odd_interior<DIM, T>(slot, i, a.g.n[0], a.g.n[0] * a.g.n[1], a.inv_s, f);
+  else
+    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+  C S, u[3];
+  moments<DIM, C>(f, a.g.rho0, S, u);
+  C* us = const_cast<C*>(a.ustar) + (size_t)i * a.vd;
+#pragma unroll
+  for (int c = 0; c < DIM; c++) us[c] = u[c];
+}
 
 // Momentum and angular momentum of the fluid inside each particle volume,
 // P = sum chi rho0 u*, L = sum chi (x - X_c) x rho0 u*, with chi = clamp(R + 1/2 - |x - X_c|,
 // 0, 1): the interior-fluid terms F_f, T_f of Eqs. 14-15 are their changes per step.
 // One workgroup per particle, FP64 accumulation and a fixed-order reduction.
-template <int DIM, class T, int PAR>
+template <int DIM, class T, int PAR, int FROMU>
 __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>::C> a) {
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
@@ -211,10 +241,16 @@ __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>
     if (chi <= 0.0) continue;
     chi = chi > 1.0 ? 1.0 : chi;
     int i = x + a.g.n[0] * (y + a.g.n[1] * z);
-    C f[L::Q];
-    load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
-    C S, us[3];
-    moments<DIM, C>(f, a.g.rho0, S, us);
+    C us[3] = {C(0), C(0), C(0)};
+    if (FROMU) {
+#pragma unroll
+      for (int c = 0; c < DIM; c++) us[c] = a.ustar[(size_t)i * a.vd + c];
+    } else {
+      C f[L::Q];
+      load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
+      C S;
+      moments<DIM, C>(f, a.g.rho0, S, us);
+    }
     double m[3] = {chi * (rho0 * double(us[0])), chi * (rho0 * double(us[1])),
                    DIM == 3 ? chi * (rho0 * double(us[2])) : 0.0};
     acc[0] += m[0];
@@ -319,7 +355,7 @@ struct RunScatter {
 
 template <int DIM, class T>
 struct RunInterior {
-  static void run(iblbm_ctx* c, double* P, double* Lm) {
+  static InteriorArgs<typename Store<T>::C> args(iblbm_ctx* c, double* P, double* Lm) {
     using C = typename Store<T>::C;
     InteriorArgs<C> a;
     a.g = make_geo<C>(c);
@@ -329,17 +365,42 @@ struct RunInterior {
     a.D = c->D;
     a.P = P;
     a.L = Lm;
-    if (c->parity == 0)
-      hipLaunchKernelGGL((k_interior<DIM, T, 0>), dim3(c->np), dim3(256), 0, c->stream, a);
+    a.ustar = (const C*)c->ustar;
+    a.vd = c->vd;
+    return a;
+  }
+  static void run(iblbm_ctx* c, double* P, double* Lm, bool from_u) {
+    auto a = args(c, P, Lm);
+    if (from_u)
+      hipLaunchKernelGGL((k_interior<DIM, T, 0, 1>), dim3(c->np), dim3(256), 0, c->stream, a);
+    else if (c->parity == 0)
+      hipLaunchKernelGGL((k_interior<DIM, T, 0, 0>), dim3(c->np), dim3(256), 0, c->stream, a);
     else
-      hipLaunchKernelGGL((k_interior<DIM, T, 1>), dim3(c->np), dim3(256), 0, c->stream, a);
+      hipLaunchKernelGGL((k_interior<DIM, T, 1, 0>), dim3(c->np), dim3(256), 0, c->stream, a);
+  }
+};
+
+template <int DIM, class T>
+struct RunUstarAll {
+  static void run(iblbm_ctx* c) {
+    auto a = RunInterior<DIM, T>::args(c, nullptr, nullptr);
+    int nbx = (c->cfg.n[0] + 255) / 256;
+    unsigned nblk = (unsigned)((long long)nbx * c->cfg.n[1] * c->cfg.n[2]);
+    if (c->parity == 0)
+      hipLaunchKernelGGL((k_ustar_all<DIM, T, 0>), dim3(nblk), dim3(256), 0, c->stream, a, nbx);
+    else
+      hipLaunchKernelGGL((k_ustar_all<DIM, T, 1>), dim3(nblk), dim3(256), 0, c->stream, a, nbx);
   }
 };
 
 }  // namespace
 
-void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L) {
-  if (c->np > 0) dispatch<RunInterior>(c, P, L);
+void lbm_interior_momentum(iblbm_ctx* c, double* P, double* L, bool from_ustar) {
+  if (c->np > 0) dispatch<RunInterior>(c, P, L, from_ustar);
+}
+void lbm_ustar_all(iblbm_ctx* c) {
+  dispatch<RunUstarAll>(c);
+  c->ustar_valid = true;
 }
 
 void lbm_collide_stream(iblbm_ctx* c) { dispatch<RunCollide>(c); }
@@ -352,8 +413,10 @@ void lbm_get_pdfs(iblbm_ctx* c, double* f) {
 void lbm_set_pdfs(iblbm_ctx* c, const double* f) {
   dispatch<RunScatter>(c, f, (const double*)nullptr, (const double*)nullptr);
   c->parity = 0;
+  c->ustar_valid = false;
 }
 void lbm_init_equilibrium(iblbm_ctx* c, const double* p, const double* u) {
   dispatch<RunScatter>(c, (const double*)nullptr, p, u);
   c->parity = 0;
+  c->ustar_valid = false;
 }
