@@ -160,6 +160,8 @@ struct iblbm_ctx {
   int* pair_nup = nullptr;    // np
   int* pair_all = nullptr;    // np x PAIR_CAP all partners, ascending
   int* pair_nall = nullptr;   // np
+  uint16_t* tlist = nullptr;  // np x box_cap: touched box nodes of each particle, ascending
+  int* tcount = nullptr;      // np: entries of tlist per particle
   // status and statistics
   int* dstatus = nullptr;     // [0] flags, [1] truncated (int64 at [2..3]), ...
   double* dstats = nullptr;   // [0] slip sum of squares

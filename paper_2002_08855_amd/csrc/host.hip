@@ -537,6 +537,10 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     if (c->pair_nup) dfree(c, c->pair_nup);
     if (c->pair_all) dfree(c, c->pair_all);
     if (c->pair_nall) dfree(c, c->pair_nall);
+    if (c->tlist) dfree(c, c->tlist);
+    if (c->tcount) dfree(c, c->tcount);
+    c->tlist = dzeros<uint16_t>(c, (size_t)np * (c->box_cap <= 65536 ? c->box_cap : 1));
+    c->tcount = dzeros<int>(c, (size_t)np);
     c->cell_of = dzeros<int>(c, 3 * (size_t)np);
     c->pair_up = dzeros<int>(c, (size_t)np * PAIR_CAP);
     c->pair_nup = dzeros<int>(c, (size_t)np);

@@ -354,6 +354,8 @@ struct LdsArgs {
   int nwx;         // words per row
   const int* cond; // run only when *cond != 0 (if set)
   int mcap;        // points of the largest particle
+  uint16_t* tlist; // touched box nodes per particle (cap entries each), ascending
+  int* tcount;
   // PDF access for the first pass
   Geo<C> geo;
   SlotPtrs slot;
@@ -491,6 +493,42 @@ __host__ __device__ inline InterpLayout interp_layout(int dim, size_t cs, int ca
   return L;
 }
 
+// List the flagged nodes of a box in ascending order into out[] (ballot compaction: each
+// wave scans one chunk of the box, then writes at its offset); returns the count.  The
+// whole block calls it; wcnt holds 17 ints.
+__device__ inline int list_flags(const uint8_t* flag, int n, uint16_t* out, int* wcnt) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int chunk = ((n + nw - 1) / nw + 63) & ~63;
+  const int c0 = wid * chunk, c1 = c0 + chunk < n ? c0 + chunk : n;
+  int cnt = 0;
+  for (int t0 = c0; t0 < c1; t0 += 64) {
+    const int t = t0 + lane;
+    cnt += __popcll(__ballot(t < c1 && flag[t]));
+  }
+  if (lane == 0) wcnt[wid] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int v = 0; v < nw; v++) {
+      int k = wcnt[v];
+      wcnt[v] = s;
+      s += k;
+    }
+    wcnt[16] = s;
+  }
+  __syncthreads();
+  int pos = wcnt[wid];
+  for (int t0 = c0; t0 < c1; t0 += 64) {
+    const int t = t0 + lane;
+    const bool f = t < c1 && flag[t];
+    const unsigned long long m = __ballot(f);
+    if (f) out[pos + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)t;
+    pos += __popcll(m);
+  }
+  __syncthreads();
+  return wcnt[16];
+}
+
 // Set the flagged nodes of a particle's box in the band bitmap, one lane per box row and
 // one atomic per (row, 32-node word).
 template <int DIM>
@@ -515,14 +553,16 @@ __device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b
 }
 
 // Band of this step for the per-particle path: flag the support nodes of every point of
-// the particle in LDS, clear the force there, and set them in the band bitmap with one
-// atomic per (row, 32-node word) of the particle's box.  u* comes from the lattice pass
-// after the previous collision.
+// the particle in LDS, list them in ascending order for the forcing passes of the step,
+// clear the force there, and set them in the band bitmap with one atomic per (row,
+// 32-node word) of the particle's box.  u* comes from the lattice pass after the
+// previous collision.
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
-  uint8_t* flag = reinterpret_cast<uint8_t*>(smem_d);
+  int* wcnt = reinterpret_cast<int*>(smem_d);
+  uint8_t* flag = reinterpret_cast<uint8_t*>(wcnt + 20);
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
@@ -538,8 +578,11 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
     visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < b.n; t += blockDim.x) {
-    if (!flag[t]) continue;
+  uint16_t* tl = a.tlist + (size_t)p * a.cap;
+  const int ntouch = list_flags(flag, b.n, tl, wcnt);
+  if (threadIdx.x == 0) a.tcount[p] = ntouch;
+  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
+    const int t = tl[j];
     int x = b.lo[0] + t % b.B[0];
     int y = b.lo[1] + (t / b.B[0]) % b.B[1];
     int z = b.lo[2] + t / (b.B[0] * b.B[1]);
@@ -551,11 +594,12 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
 }
 
 // Interpolation (+ point force) for one forcing pass through the particle's LDS box.
-// The touched nodes are flagged (one lane per point), listed in ascending order (ballot
-// compaction, so that neighbouring lanes stage neighbouring nodes), staged into LDS as
-// u = u* + f/(2 rho0) (Eq. 7), and gathered by one lane per point.  u* and the cleared
-// force come from the band pass, or, with FIRST, are made here from the PDFs of the
-// touched nodes, which also enter the band bitmap.
+// The touched nodes of the step are listed in ascending order (so that neighbouring
+// lanes stage neighbouring nodes), staged into LDS as u = u* + f/(2 rho0) (Eq. 7), and
+// gathered by one lane per point.  The list, u* and the cleared force come from the
+// marking kernel and the lattice u* pass, or, with FIRST, are made here: the nodes are
+// flagged (one lane per point) and listed by ballot compaction, u* comes from their PDFs,
+// and they enter the band bitmap.
 template <int DIM, class T, int PAR, int FIRST>
 __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Store<T>::C> a) {
   using C = typename Store<T>::C;
@@ -574,52 +618,34 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
   if (b.n > a.cap) return;  // the host sizes cap for the largest particle
-  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
-  __syncthreads();
   int m0 = a.mstart[p], mc = a.mcount[p];
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    PointWeights<C> pw;
-    point_weights<DIM, C>(a.g.kind, X, pw);
-    visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
-  }
-  __syncthreads();
-  // list the flagged nodes in ascending order: each wave scans one chunk of the box
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int chunk = ((b.n + nw - 1) / nw + 63) & ~63;
-  const int c0 = wid * chunk, c1 = c0 + chunk < b.n ? c0 + chunk : b.n;
-  int cnt = 0;
-  for (int t0 = c0; t0 < c1; t0 += 64) {
-    const int t = t0 + lane;
-    cnt += __popcll(__ballot(t < c1 && flag[t]));
-  }
-  if (lane == 0) wcnt[wid] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int v = 0; v < nw; v++) {
-      int n = wcnt[v];
-      wcnt[v] = s;
-      s += n;
+  uint16_t* tl = a.tlist + (size_t)p * a.cap;
+  int ntouch;
+  const uint16_t* nodes;
+  if (FIRST) {
+    // the touched nodes of this step, kept for the later passes
+    for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
+    __syncthreads();
+    for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
+      double X[3], Ub[3];
+      marker_pos_vel(a.P, k, X, Ub, DIM);
+      PointWeights<C> pw;
+      point_weights<DIM, C>(a.g.kind, X, pw);
+      visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
     }
-    wcnt[16] = s;
+    __syncthreads();
+    ntouch = list_flags(flag, b.n, list, wcnt);
+    if (threadIdx.x == 0) a.tcount[p] = ntouch;
+    for (int j = threadIdx.x; j < ntouch; j += blockDim.x) tl[j] = list[j];
+    nodes = list;
+  } else {
+    ntouch = a.tcount[p];
+    nodes = tl;
   }
-  __syncthreads();
-  int pos = wcnt[wid];
-  for (int t0 = c0; t0 < c1; t0 += 64) {
-    const int t = t0 + lane;
-    const bool f = t < c1 && flag[t];
-    const unsigned long long m = __ballot(f);
-    if (f) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)t;
-    pos += __popcll(m);
-  }
-  __syncthreads();
-  const int ntouch = wcnt[16];
   T* slot[L::Q - 1];
   if (FIRST) slots_of<DIM, T>(a.slot, slot);
   for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
-    const int t = list[j];
+    const int t = nodes[j];
     int x = b.lo[0] + t % b.B[0];
     int y = b.lo[1] + (t / b.B[0]) % b.B[1];
     int z = b.lo[2] + t / (b.B[0] * b.B[1]);
@@ -702,6 +728,7 @@ struct Fixed<double> {
 };
 
 // dynamic LDS of the spreading kernel: Fixed<C>::U acc[DIM][cap], then double red[16]
+// and uint16 list[cap]
 __host__ __device__ inline size_t spread_acc_bytes(int dim, size_t cs, int cap) {
   return ((size_t)dim * cap * (cs == 8 ? 8 : 4) + 7) & ~(size_t)7;
 }
@@ -710,8 +737,8 @@ __host__ __device__ inline size_t spread_acc_bytes(int dim, size_t cs, int cap) 
 // one lane per point.  The box holds fixed-point sums: the scale 2^e is chosen per
 // particle so that the sum of max_c |F_c drs ds| over all points, times the largest
 // product of 1-D weights, stays below 2^BITS; no node sum can exceed it, so none
-// overflows.  Each touched node then reaches the global force once, one lane per
-// (node, component) so that neighbouring lanes hit neighbouring addresses.
+// overflows.  Each touched node of the step's list then reaches the global force once,
+// one lane per (node, component) so that neighbouring lanes hit neighbouring addresses.
 template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   using FX = Fixed<C>;
@@ -728,9 +755,17 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   // the host sizes the box and the block for the largest particle
   if (b.n > a.cap || mc > (int)blockDim.x) return;
   const int kind = a.g.kind, width = a.g.width;
-  for (int t = threadIdx.x; t < b.n; t += blockDim.x)
+  // the touched nodes of the step (listed by the marking kernel or the first pass),
+  // copied into LDS
+  uint16_t* tl = reinterpret_cast<uint16_t*>(red + 16);
+  const uint16_t* gl = a.tlist + (size_t)p * a.cap;
+  const int ntouch = a.tcount[p];
+  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
+    const int t = gl[j];
+    tl[j] = (uint16_t)t;
 #pragma unroll
     for (int c = 0; c < DIM; c++) acc[c * a.cap + t] = U(0);
+  }
   // this lane's point: 1-D weights, first support node, force times drs*ds (Eq. 13)
   const int kl = threadIdx.x;
   const bool has = kl < mc;
@@ -799,10 +834,11 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
         }
   }
   __syncthreads();
-  const int nu = b.n * a.vd;
+  const int nu = ntouch * a.vd;
   for (int u = threadIdx.x; u < nu; u += blockDim.x) {
-    const int t = u / a.vd, c = u - t * a.vd;
+    const int j = u / a.vd, c = u - j * a.vd;
     if (c >= DIM) continue;
+    const int t = tl[j];
     const U q = acc[c * a.cap + t];
     if (q == U(0)) continue;
     int x = b.lo[0] + t % b.B[0];
@@ -931,6 +967,8 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.nwx = (int)c->nwx;
   a.cond = c->cond;
   a.mcap = max_points(c);
+  a.tlist = c->tlist;
+  a.tcount = c->tcount;
   a.geo = make_geo<C>(c);
   a.slot = make_slots(c);
   a.inv_s = inv_scale<T>(c);
@@ -948,7 +986,8 @@ int lds_threads(const iblbm_ctx* c) {
 // and component plus a small reduction area
 size_t lds_bytes(const iblbm_ctx* c, size_t cs, bool interp) {
   if (interp) return interp_layout(c->dim, cs, c->box_cap).total;
-  return spread_acc_bytes(c->dim, cs, c->box_cap) + 16 * sizeof(double);
+  return spread_acc_bytes(c->dim, cs, c->box_cap) + 16 * sizeof(double) +
+         (((size_t)c->box_cap * 2 + 7) & ~(size_t)7);
 }
 
 // interpolation: one lane per point; in 3-D also enough lanes to stage the touched
@@ -978,6 +1017,9 @@ struct RunInterp {
   }
   template <int PAR, int FIRST>
   static void go(iblbm_ctx* c, LdsArgs<typename Store<T>::C>& a, size_t bytes) {
+    using C = typename Store<T>::C;
+    // later passes stage from the step's list: only the velocity box is needed
+    if (!FIRST) bytes = ((size_t)DIM * c->box_cap * sizeof(C) + 7) & ~(size_t)7;
     auto k = k_interp_lds<DIM, T, PAR, FIRST>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL(k, dim3(c->np), dim3(interp_threads(c)), bytes, c->stream, a);
@@ -990,7 +1032,7 @@ struct RunMarkLds {
   static void run(iblbm_ctx* c) {
     using C = typename Store<T>::C;
     auto a = make_lds_args<T>(c, 0, 0);
-    size_t bytes = ((size_t)c->box_cap + 3) & ~(size_t)3;
+    size_t bytes = 20 * sizeof(int) + (((size_t)c->box_cap + 3) & ~(size_t)3);
     hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
   }
 };
