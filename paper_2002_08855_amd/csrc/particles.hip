@@ -219,13 +219,14 @@ struct LoadArgs {
   int update;  // 0: loads only
 };
 
-// One workgroup per particle: F_h = -sum F_k dV_k, T_h = -sum r_k x F_k dV_k in FP64 with a
-// fixed reduction tree, then Eqs. 14-15 with the interior-fluid terms
-// F_f = P^n - P^(n-1), T_f = L^n - L^(n-1), the hydrodynamic load averaged over the
-// current and previous steps, explicit Euler for U, Omega and the trapezoid rule for X.
+// One workgroup per particle: F_h = -sum F_k dV_k, T_h = -sum r_k x F_k dV_k in FP64 in a
+// fixed order (butterfly within each wavefront, then the wavefronts in order), then
+// Eqs. 14-15 with the interior-fluid terms F_f = P^n - P^(n-1), T_f = L^n - L^(n-1), the
+// hydrodynamic load averaged over the current and previous steps, explicit Euler for U,
+// Omega and the trapezoid rule for X.
 template <class C>
 __global__ __launch_bounds__(256) void k_loads_newton(LoadArgs<C> a) {
-  __shared__ double red[6][256];
+  __shared__ double red[6][4];
   int p = blockIdx.x;
   int m0 = a.mstart[p], mc = a.mcount[p];
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -248,14 +249,15 @@ __global__ __launch_bounds__(256) void k_loads_newton(LoadArgs<C> a) {
       Fp[2] = Fk[2];
     }
   }
-  for (int k = 0; k < 6; k++) red[k][threadIdx.x] = acc[k];
+  // butterfly sums within each wavefront, then the wavefront partials in a fixed order
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 6; k++) acc[k] += __shfl_xor(acc[k], o, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; k++) red[k][threadIdx.x >> 6] = acc[k];
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int k = 0; k < 6; k++) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-    __syncthreads();
-  }
   if (threadIdx.x != 0) return;
+  for (int v = 1; v < (int)(blockDim.x >> 6); v++)
+    for (int k = 0; k < 6; k++) red[k][0] += red[k][v];
   const PartArgs& q = a.pa;
   for (int d = 0; d < 3; d++) {
     q.Fh[3 * p + d] = red[d][0];
@@ -353,7 +355,11 @@ void run_loads(iblbm_ctx* c, int update) {
   a.I = c->I;
   a.X = c->X;
   a.update = update;
-  hipLaunchKernelGGL((k_loads_newton<C>), dim3(c->np), dim3(256), 0, c->stream, a);
+  // one wavefront per 64 points of the largest particle, at most four
+  int mx = 1;
+  for (int m : c->hcount) mx = m > mx ? m : mx;
+  int threads = mx <= 64 ? 64 : (mx <= 128 ? 128 : 256);
+  hipLaunchKernelGGL((k_loads_newton<C>), dim3(c->np), dim3(threads), 0, c->stream, a);
 }
 
 }  // namespace
