@@ -165,7 +165,12 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
                                  pass (default in 2-D); the results are identical */
 #define IBLBM_OPT_STATS_EVERY 3 /* replaces the configuration's stats_every (>= 0) */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
-/* Capture each step as a HIP graph and replay it (0 = plain launches). */
+/* on != 0: run steps through HIP graphs.  A step's kernel launches are captured the
+ * first time its (PDF parity, band-bitmap buffer) pair occurs and replayed afterwards;
+ * changes of state (particles, PDFs, options, MLP) drop the graphs.  Timed steps and
+ * steps that gather the slip statistic still launch kernel by kernel.  Results equal
+ * those of plain launches up to the order of the force spreading's float atomics.
+ * on = 0 (default): plain launches. */
 iblbm_status iblbm_set_graph(iblbm_ctx* ctx, int32_t on);
 
 /* Learned forcing (MLP 10-64-64-3 with tanh hidden layers).  params: 5059 floats

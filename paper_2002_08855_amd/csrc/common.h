@@ -186,7 +186,11 @@ struct iblbm_ctx {
   long long launches[IBLBM_NGROUPS] = {0};
   // graphs
   bool use_graph = false;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // one captured step per (PDF parity, band-bitmap buffer), and the host-side flags the
+  // captured step left behind
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool gend_band_pending[4] = {false, false, false, false};
+  bool gend_ustar_valid[4] = {false, false, false, false};
   bool graph_dirty = true;
   // allocations
   std::vector<void*> allocs;
@@ -218,6 +222,7 @@ void part_cells_pairs(iblbm_ctx* c);
 void part_loads_newton(iblbm_ctx* c);
 void mlp_features(iblbm_ctx* c);
 void ibm_band_redo(iblbm_ctx* c);
+void ibm_prepare_launches(iblbm_ctx* c);
 void mlp_infer(iblbm_ctx* c);
 
 // timing helpers (host.hip)

@@ -222,6 +222,57 @@ void enqueue_step(iblbm_ctx* c) {
   c->step++;
 }
 
+void drop_graphs(iblbm_ctx* c) {
+  for (int k = 0; k < 4; k++)
+    if (c->gexec[k]) {
+      (void)hipGraphExecDestroy(c->gexec[k]);
+      c->gexec[k] = nullptr;
+    }
+}
+
+// One step through a HIP graph.  The first time a (PDF parity, bitmap buffer) pair
+// occurs, the step's launches are captured from enqueue_step (which also advances the
+// host-side state) and instantiated; later steps with the same pair replay the graph
+// and restore the host-side state the captured step left behind.  The step contains
+// kernel launches only (no memory set or copy nodes).
+void step_graph(iblbm_ctx* c) {
+  if (c->graph_dirty) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->graph_dirty = false;
+  }
+  const int key = (c->parity & 1) * 2 + (int)(c->step & 1);
+  if (!c->gexec[key]) {
+    ibm_prepare_launches(c);  // kernel attributes are set before capture
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_step(c);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    hipError_t e = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec[key] = nullptr;
+      throw Fail{fail(c, IBLBM_E_DEVICE, "graph instantiation failed")};
+    }
+    c->gend_band_pending[key] = c->band_pending;
+    c->gend_ustar_valid[key] = c->ustar_valid;
+    HIPCHK(hipGraphLaunch(c->gexec[key], c->stream));
+    return;
+  }
+  HIPCHK(hipGraphLaunch(c->gexec[key], c->stream));
+  c->fbuf = (int)(c->step & 1);
+  c->parity ^= 1;
+  c->step++;
+  c->band_pending = c->gend_band_pending[key];
+  c->ustar_valid = c->gend_ustar_valid[key];
+}
+
 }  // namespace
 
 void tbegin(iblbm_ctx* c, int group) {
@@ -316,8 +367,7 @@ void iblbm_destroy(iblbm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto e : c->ev) (void)hipEventDestroy(e);
-  for (int k = 0; k < 2; k++)
-    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+  drop_graphs(c);
   std::vector<void*> all = c->allocs;
   for (void* p : all) dfree(c, p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -569,7 +619,13 @@ iblbm_status iblbm_step(iblbm_ctx* c, int32_t nsteps) {
   try {
     HIPCHK(hipSetDevice(c->device));
     for (int k = 0; k < nsteps; k++) {
-      enqueue_step(c);
+      // graphs replay plain steps; timed steps and steps that gather the slip
+      // statistic are launched one kernel at a time
+      const bool stats_step = c->cfg.stats_every > 0 && c->step % c->cfg.stats_every == 0;
+      if (c->use_graph && !c->timing && !stats_step)
+        step_graph(c);
+      else
+        enqueue_step(c);
       if (c->timing && c->ev_used > 4000) flush_timing(c);
     }
     HIPCHK(hipGetLastError());

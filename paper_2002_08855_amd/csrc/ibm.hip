@@ -19,6 +19,9 @@
 // In the per-particle kernels one lane owns one point: it evaluates the twelve 1-D
 // weights of its support once and walks the 4x4x4 support, accumulating in registers
 // (interpolation) or with LDS atomics (spreading).
+#include <mutex>
+#include <set>
+
 #include "pdf_access.h"
 
 namespace {
@@ -999,8 +1002,24 @@ int interp_threads(const iblbm_ctx* c) {
   return (int)std::min<long long>(std::max<long long>(t, 64), LDS_THREADS);
 }
 
+// Raise a kernel's dynamic-LDS limit to the device maximum, once per kernel: a
+// host-side attribute, so that launches recorded into a graph set none.
+void raise_lds_limit(const void* k, int bytes) {
+  static std::mutex mu;
+  static std::set<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(k)) return;
+  (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  done.insert(k);
+}
+
 template <int DIM, class T>
 struct RunInterp {
+  static void limits(iblbm_ctx* c) {
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 0>, c->lds_max);
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 1>, c->lds_max);
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 1, 1>, c->lds_max);
+  }
   static void run(iblbm_ctx* c, int first, int mode, bool* done) {
     using C = typename Store<T>::C;
     *done = false;
@@ -1021,7 +1040,7 @@ struct RunInterp {
     // later passes stage from the step's list: only the velocity box is needed
     if (!FIRST) bytes = ((size_t)DIM * c->box_cap * sizeof(C) + 7) & ~(size_t)7;
     auto k = k_interp_lds<DIM, T, PAR, FIRST>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    raise_lds_limit((const void*)k, c->lds_max);
     hipLaunchKernelGGL(k, dim3(c->np), dim3(interp_threads(c)), bytes, c->stream, a);
   }
 };
@@ -1038,6 +1057,14 @@ struct RunMarkLds {
 };
 
 template <int DIM, class T>
+struct RunLdsLimits {
+  static void run(iblbm_ctx* c) {
+    RunInterp<DIM, T>::limits(c);
+    raise_lds_limit((const void*)k_spread_lds<DIM, typename Store<T>::C>, c->lds_max);
+  }
+};
+
+template <int DIM, class T>
 struct RunSpread {
   static void run(iblbm_ctx* c, bool* done) {
     using C = typename Store<T>::C;
@@ -1046,7 +1073,7 @@ struct RunSpread {
     if (!ibm_uses_lds(c)) return;
     auto a = make_lds_args<T>(c, 0, 0);
     auto k = k_spread_lds<DIM, C>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    raise_lds_limit((const void*)k, c->lds_max);
     hipLaunchKernelGGL(k, dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
     *done = true;
   }
@@ -1148,6 +1175,8 @@ void ibm_band(iblbm_ctx* c) {
 
 // Recompute u* and clear the force at the band before a forcing redo (the per-particle
 // path does it in its first interpolation pass).
+void ibm_prepare_launches(iblbm_ctx* c) { dispatch<RunLdsLimits>(c); }
+
 void ibm_band_redo(iblbm_ctx* c) {
   if (c->np == 0) return;
   if (ibm_uses_lds(c)) {

@@ -414,9 +414,11 @@ void lbm_set_pdfs(iblbm_ctx* c, const double* f) {
   dispatch<RunScatter>(c, f, (const double*)nullptr, (const double*)nullptr);
   c->parity = 0;
   c->ustar_valid = false;
+  c->graph_dirty = true;
 }
 void lbm_init_equilibrium(iblbm_ctx* c, const double* p, const double* u) {
   dispatch<RunScatter>(c, (const double*)nullptr, p, u);
   c->parity = 0;
   c->ustar_valid = false;
+  c->graph_dirty = true;
 }

@@ -463,6 +463,7 @@ iblbm_status iblbm_set_mlp(iblbm_ctx* c, const float* params, const float* norm)
     return IBLBM_E_DEVICE;
   }
   c->has_mlp = true;
+  c->graph_dirty = true;
   return IBLBM_OK;
 }
 
