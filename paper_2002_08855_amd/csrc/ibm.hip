@@ -367,6 +367,39 @@ struct LdsArgs {
 
 constexpr int LDS_THREADS = 1024;
 
+// List entries a lane loads before it uses any of them, so that their global-memory
+// latencies overlap.
+constexpr int LIST_BATCH = 4;
+
+// The vector of a node (ustar, facc): vd consecutive values, 2 in 2-D and 4 in 3-D,
+// loaded as one aligned vector.
+template <class C, int DIM>
+struct NodeVec;
+template <>
+struct NodeVec<float, 2> {
+  using T = float2;
+};
+template <>
+struct NodeVec<float, 3> {
+  using T = float4;
+};
+template <>
+struct NodeVec<double, 2> {
+  using T = double2;
+};
+template <>
+struct NodeVec<double, 3> {
+  using T = double4;
+};
+template <int DIM, class C>
+__device__ __forceinline__ typename NodeVec<C, DIM>::T load_node(const C* v, size_t i) {
+  return *reinterpret_cast<const typename NodeVec<C, DIM>::T*>(v + i);
+}
+template <class C, class V>
+__device__ __forceinline__ C comp(const V& v, int c) {
+  return reinterpret_cast<const C*>(&v)[c];
+}
+
 // 1-D weights of a point's support (the factors of Eq. 12).  With f the offset of X
 // past its first support node (Peskin 4-point) or from its nearest node (Roma
 // 3-point) and s the one square root both kernels need, the weight of support node q
@@ -620,8 +653,24 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
   int m0 = a.mstart[p], mc = a.mcount[p];
+  // the host sizes cap and the block for the largest particle
+  if (b.n > a.cap || mc > (int)blockDim.x) return;
+  // this lane's point, loaded and weighted before the box is staged so that the
+  // latencies overlap; with an accumulating pass also its force so far
+  const int k = m0 + (int)threadIdx.x;
+  const bool has = (int)threadIdx.x < mc;
+  double X[3] = {0, 0, 0}, Ub[3] = {0, 0, 0};
+  PointWeights<C> pw;
+  C Fold[3] = {C(0), C(0), C(0)};
+  if (has) {
+    marker_pos_vel(a.P, k, X, Ub, DIM);
+    if (a.mode == 0 && !a.first_pass) {
+#pragma unroll
+      for (int c = 0; c < DIM; c++) Fold[c] = a.F[4 * (size_t)k + c];
+    }
+    point_weights<DIM, C>(a.g.kind, X, pw);
+  }
   uint16_t* tl = a.tlist + (size_t)p * a.cap;
   int ntouch;
   const uint16_t* nodes;
@@ -629,13 +678,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
     // the touched nodes of this step, kept for the later passes
     for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
     __syncthreads();
-    for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-      double X[3], Ub[3];
-      marker_pos_vel(a.P, k, X, Ub, DIM);
-      PointWeights<C> pw;
-      point_weights<DIM, C>(a.g.kind, X, pw);
-      visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
-    }
+    if (has) visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
     __syncthreads();
     ntouch = list_flags(flag, b.n, list, wcnt);
     if (threadIdx.x == 0) a.tcount[p] = ntouch;
@@ -647,14 +690,15 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   }
   T* slot[L::Q - 1];
   if (FIRST) slots_of<DIM, T>(a.slot, slot);
-  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
-    const int t = nodes[j];
-    int x = b.lo[0] + t % b.B[0];
-    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
-    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
-    const int ii = x + a.g.n[0] * (y + a.g.n[1] * z);
-    const size_t i = (size_t)ii * a.vd;
-    if (FIRST) {
+  if (FIRST) {
+    // u* from the PDFs at the listed nodes (Eqs. 4-5); the force there starts at zero
+    for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
+      const int t = nodes[j];
+      int x = b.lo[0] + t % b.B[0];
+      int y = b.lo[1] + (t / b.B[0]) % b.B[1];
+      int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+      const int ii = x + a.g.n[0] * (y + a.g.n[1] * z);
+      const size_t i = (size_t)ii * a.vd;
       C f[L::Q];
       load_all<DIM, T, PAR>(slot, a.geo, x, y, z, ii, a.inv_s, f);
       C S, u[3];
@@ -665,20 +709,40 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
         a.ustar[i + c] = u[c];
         a.facc[i + c] = C(0);
       }
-    } else {
+    }
+  } else {
+    // u* + F / (2 rho0) at the listed nodes, LIST_BATCH entries per lane at a time
+    for (int j0 = threadIdx.x; j0 < ntouch; j0 += LIST_BATCH * blockDim.x) {
+      int t[LIST_BATCH];
 #pragma unroll
-      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = a.ustar[i + c] + a.facc[i + c] * a.half_inv_rho;
+      for (int u = 0; u < LIST_BATCH; u++) {
+        const int j = j0 + u * (int)blockDim.x;
+        t[u] = j < ntouch ? (int)nodes[j] : -1;
+      }
+      typename NodeVec<C, DIM>::T us[LIST_BATCH], fa[LIST_BATCH];
+#pragma unroll
+      for (int u = 0; u < LIST_BATCH; u++) {
+        if (t[u] < 0) continue;
+        const int x = b.lo[0] + t[u] % b.B[0];
+        const int y = b.lo[1] + (t[u] / b.B[0]) % b.B[1];
+        const int z = b.lo[2] + t[u] / (b.B[0] * b.B[1]);
+        const size_t i = (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
+        us[u] = load_node<DIM>(a.ustar, i);
+        fa[u] = load_node<DIM>(a.facc, i);
+      }
+#pragma unroll
+      for (int u = 0; u < LIST_BATCH; u++) {
+        if (t[u] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < DIM; c++) ub[c * a.cap + t[u]] = comp<C>(us[u], c) + comp<C>(fa[u], c) * a.half_inv_rho;
+      }
     }
   }
   if (FIRST) band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
   __syncthreads();
   // gather each support from LDS (Eq. 9 with Eq. 12) and form the point force (Eq. 10)
   unsigned long long ntr = 0;
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    PointWeights<C> pw;
-    point_weights<DIM, C>(a.g.kind, X, pw);
+  if (has) {
     C acc[3] = {0, 0, 0};
     ntr += visit_support<DIM, C>(a.g, b, pw, [&](int loc, C w) {
 #pragma unroll
@@ -690,7 +754,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
       for (int c = 0; c < DIM; c++) {
         C d = a.two_rho * (C(Ub[c]) - acc[c]);
         dF[c] = d;
-        F[c] = a.first_pass ? d : F[c] + d;
+        F[c] = a.first_pass ? d : Fold[c] + d;
       }
     } else if (a.mode == 1) {
       double s2 = 0;
@@ -758,17 +822,6 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   // the host sizes the box and the block for the largest particle
   if (b.n > a.cap || mc > (int)blockDim.x) return;
   const int kind = a.g.kind, width = a.g.width;
-  // the touched nodes of the step (listed by the marking kernel or the first pass),
-  // copied into LDS
-  uint16_t* tl = reinterpret_cast<uint16_t*>(red + 16);
-  const uint16_t* gl = a.tlist + (size_t)p * a.cap;
-  const int ntouch = a.tcount[p];
-  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
-    const int t = gl[j];
-    tl[j] = (uint16_t)t;
-#pragma unroll
-    for (int c = 0; c < DIM; c++) acc[c * a.cap + t] = U(0);
-  }
   // this lane's point: 1-D weights, first support node, force times drs*ds (Eq. 13)
   const int kl = threadIdx.x;
   const bool has = kl < mc;
@@ -797,6 +850,26 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
     for (int c = 0; c < DIM; c++) {
       F[c] = d[c] * dV;
       mag = fmax(mag, fabs(double(F[c])));
+    }
+  }
+  // the touched nodes of the step (listed by the marking kernel or the first pass),
+  // copied into LDS after the point loads above are issued, so that the latencies overlap
+  uint16_t* tl = reinterpret_cast<uint16_t*>(red + 16);
+  const uint16_t* gl = a.tlist + (size_t)p * a.cap;
+  const int ntouch = a.tcount[p];
+  for (int j0 = threadIdx.x; j0 < ntouch; j0 += LIST_BATCH * blockDim.x) {
+    int t[LIST_BATCH];
+#pragma unroll
+    for (int u = 0; u < LIST_BATCH; u++) {
+      const int j = j0 + u * (int)blockDim.x;
+      t[u] = j < ntouch ? (int)gl[j] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < LIST_BATCH; u++) {
+      if (t[u] < 0) continue;
+      tl[j0 + u * blockDim.x] = (uint16_t)t[u];
+#pragma unroll
+      for (int c = 0; c < DIM; c++) acc[c * a.cap + t[u]] = U(0);
     }
   }
   for (int o = 32; o > 0; o >>= 1) mag += __shfl_xor(mag, o, 64);
@@ -837,10 +910,9 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
         }
   }
   __syncthreads();
-  const int nu = ntouch * a.vd;
+  const int nu = ntouch * DIM;
   for (int u = threadIdx.x; u < nu; u += blockDim.x) {
-    const int j = u / a.vd, c = u - j * a.vd;
-    if (c >= DIM) continue;
+    const int j = u / DIM, c = u - j * DIM;
     const int t = tl[j];
     const U q = acc[c * a.cap + t];
     if (q == U(0)) continue;
