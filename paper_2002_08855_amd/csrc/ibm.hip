@@ -311,6 +311,19 @@ __global__ void k_reset_count(int* count) { *count = 0; }
 template <int DIM>
 struct PBox {
   int lo[3], B[3], n;
+  float rb0, rb01;  // 1 / B0 and 1 / (B0 B1)
+  // Lattice coordinates of box node t = lx + B0 (ly + B1 lz).  The quotients come from
+  // float reciprocals: for t < 2^16 the rounding error of (t + 1/2) / B stays below
+  // 2^-6 / B while the fraction of (t + 1/2) / B is at least 1/(2B) from an integer,
+  // so truncation gives the exact quotient without an integer division.
+  __device__ __forceinline__ void at(int t, int& x, int& y, int& z) const {
+    const int lz = (int)(((float)t + 0.5f) * rb01);
+    const int r = t - lz * (B[0] * B[1]);
+    const int ly = (int)(((float)r + 0.5f) * rb0);
+    x = lo[0] + r - ly * B[0];
+    y = lo[1] + ly;
+    z = lo[2] + lz;
+  }
 };
 
 // The box of nodes that the supports of a particle's points can reach.  R is widened by
@@ -333,6 +346,8 @@ __device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, in
     }
     b.n *= b.B[d];
   }
+  b.rb0 = 1.0f / (float)b.B[0];
+  b.rb01 = 1.0f / (float)(b.B[0] * b.B[1]);
   return b;
 }
 
@@ -619,9 +634,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
   if (threadIdx.x == 0) a.tcount[p] = ntouch;
   for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
     const int t = tl[j];
-    int x = b.lo[0] + t % b.B[0];
-    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
-    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+    int x, y, z;
+    b.at(t, x, y, z);
     C* fa = a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
 #pragma unroll
     for (int c = 0; c < DIM; c++) fa[c] = C(0);
@@ -694,9 +708,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
     // u* from the PDFs at the listed nodes (Eqs. 4-5); the force there starts at zero
     for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
       const int t = nodes[j];
-      int x = b.lo[0] + t % b.B[0];
-      int y = b.lo[1] + (t / b.B[0]) % b.B[1];
-      int z = b.lo[2] + t / (b.B[0] * b.B[1]);
+      int x, y, z;
+      b.at(t, x, y, z);
       const int ii = x + a.g.n[0] * (y + a.g.n[1] * z);
       const size_t i = (size_t)ii * a.vd;
       C f[L::Q];
@@ -723,9 +736,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
 #pragma unroll
       for (int u = 0; u < LIST_BATCH; u++) {
         if (t[u] < 0) continue;
-        const int x = b.lo[0] + t[u] % b.B[0];
-        const int y = b.lo[1] + (t[u] / b.B[0]) % b.B[1];
-        const int z = b.lo[2] + t[u] / (b.B[0] * b.B[1]);
+        int x, y, z;
+        b.at(t[u], x, y, z);
         const size_t i = (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
         us[u] = load_node<DIM>(a.ustar, i);
         fa[u] = load_node<DIM>(a.facc, i);
@@ -911,17 +923,27 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   }
   __syncthreads();
   const int nu = ntouch * DIM;
-  for (int u = threadIdx.x; u < nu; u += blockDim.x) {
-    const int j = u / DIM, c = u - j * DIM;
-    const int t = tl[j];
-    const U q = acc[c * a.cap + t];
-    if (q == U(0)) continue;
-    int x = b.lo[0] + t % b.B[0];
-    int y = b.lo[1] + (t / b.B[0]) % b.B[1];
-    int z = b.lo[2] + t / (b.B[0] * b.B[1]);
-    if (x < 0 || x >= a.g.n[0] || y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
-    unsafeAtomicAdd(a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd + c,
-                    FX::value(q) * inv);
+  for (int u0 = threadIdx.x; u0 < nu; u0 += LIST_BATCH * blockDim.x) {
+    int t[LIST_BATCH];
+    U q[LIST_BATCH];
+#pragma unroll
+    for (int v = 0; v < LIST_BATCH; v++) {
+      const int u = u0 + v * (int)blockDim.x;
+      const int j = u / DIM, c = u - j * DIM;
+      t[v] = u < nu ? (int)tl[j] : 0;
+      q[v] = u < nu ? acc[c * a.cap + t[v]] : U(0);
+    }
+#pragma unroll
+    for (int v = 0; v < LIST_BATCH; v++) {
+      if (q[v] == U(0)) continue;
+      const int u = u0 + v * (int)blockDim.x;
+      const int c = u - (u / DIM) * DIM;
+      int x, y, z;
+      b.at(t[v], x, y, z);
+      if (x < 0 || x >= a.g.n[0] || y < 0 || y >= a.g.n[1] || z < 0 || z >= a.g.n[2]) continue;
+      unsafeAtomicAdd(a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd + c,
+                      FX::value(q[v]) * inv);
+    }
   }
 }
 
