@@ -164,6 +164,9 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
                                  (default in 3-D), 0 = inside the first interpolation
                                  pass (default in 2-D); the results are identical */
 #define IBLBM_OPT_STATS_EVERY 3 /* replaces the configuration's stats_every (>= 0) */
+#define IBLBM_OPT_TIMING_EVERY 4 /* >= 1 (default 1): with timing on, only the launches of
+                                    steps whose index is a multiple of the value carry
+                                    events, so that the events' own cost stays small */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
 /* on != 0: run steps through HIP graphs.  A step's kernel launches are captured the
  * first time its (PDF parity, band-bitmap buffer) pair occurs and replayed afterwards;

@@ -305,6 +305,10 @@ class Sim:
         """band u* in its own lattice pass (True) or in the first interpolation (False)"""
         self.set_option(2, int(on))
 
+    def set_timing_every(self, k):
+        """with timing on, time the launches of every k-th step only"""
+        self.set_option(4, int(k))
+
     def set_graph(self, on=True):
         self._check(lib().iblbm_set_graph(self.h, int(on)))
 

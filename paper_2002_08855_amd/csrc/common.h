@@ -178,6 +178,7 @@ struct iblbm_ctx {
   // timing
   bool timing = false;
   int timing_mask = 0;  // bit g: time kernel group g
+  int timing_every = 1; // time the launches of every timing_every-th step only
   bool t_open = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_group;

@@ -277,7 +277,7 @@ void step_graph(iblbm_ctx* c) {
 
 void tbegin(iblbm_ctx* c, int group) {
   c->t_open = false;
-  if (!c->timing || !((c->timing_mask >> group) & 1)) return;
+  if (!c->timing || !((c->timing_mask >> group) & 1) || c->step % c->timing_every != 0) return;
   c->t_open = true;
   if (c->ev_used + 2 > c->ev.size()) {
     for (int k = 0; k < 64; k++) {
@@ -806,6 +806,11 @@ iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
   if (option == IBLBM_OPT_BAND_PASS) {
     c->band_pass = value != 0 ? 1 : 0;
     c->graph_dirty = true;
+    return IBLBM_OK;
+  }
+  if (option == IBLBM_OPT_TIMING_EVERY) {
+    if (value < 1) return fail(c, IBLBM_E_ARG, "timing_every must be >= 1");
+    c->timing_every = value;
     return IBLBM_OK;
   }
   if (option == IBLBM_OPT_STATS_EVERY) {
