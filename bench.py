@@ -190,9 +190,10 @@ def _sim(binding, p, parts):
 
 
 def run_forms(args):
-    """The two other forms of the step on their workloads: PDFs stored as BF16 (384^3,
-    25033 spheres, volume fraction 0.40) and learned forcing (256^3, 2347 spheres, 0.30)
-    against plain 5-pass multi-direct forcing on the same workload.  The network is
+    """The other forms of the step on their workloads: PDFs stored as BF16 (384^3, 25033
+    spheres, volume fraction 0.40); the single-pass thickened-shell forcing against plain
+    MDF-3 (2048^2, 4096 disks); and learned forcing (256^3, 2347 spheres, 0.30) against
+    plain 5-pass multi-direct forcing on the same workload.  The network is
     trained here, on the GPU, on (features, converged force) pairs captured from the
     plain solver."""
     import numpy as np
@@ -214,6 +215,28 @@ def run_forms(args):
         torch.cuda.empty_cache()
     except Exception as e:  # reported, not fatal for the headline line
         forms["bf16_storage"] = {"error": repr(e)}
+    # the paper's own coupling for its particle-laden runs: one forcing pass with the
+    # shell thickened to drs = 1.9 (3-point kernel), against plain MDF-3 with the 4-point
+    # kernel, on the same lattice and particles (the sparse 2-D layout: at the dense
+    # workloads' packing the single thickened pass does not settle stably)
+    for base_name, st in (("cavity2048_sparse", max(steps, 100)),):
+        key = "btdf_single_pass"
+        try:
+            res = {}
+            for name in (base_name, base_name + "_btdf"):
+                w = inputs.workload(name)
+                p = dict(w["params"])
+                sim = _sim(binding, p, w["particles"])
+                res[name] = _timed(sim, int(np.prod(p["n"])), st, warmup)
+                res[name].update({"delta": ["peskin4", "roma3"][p["delta"]], "drs": p["drs"],
+                                  "mdf_iters": p["mdf_iters"]})
+                del sim
+                torch.cuda.empty_cache()
+            r = dict(res[base_name + "_btdf"])
+            r.update({"workload": base_name + "_btdf", "dtype": "f32", "plain_mdf3": res[base_name]})
+            forms[key] = r
+        except Exception as e:
+            forms[key] = {"error": repr(e)}
     try:
         w = inputs.workload("cavity256_learned")
         parts = w["particles"]

@@ -80,6 +80,9 @@ def workload(name: str) -> dict:
     cavity2048_f32    : 2-D 2048^2, FP32, tau 0.6, area fraction 0.40: 5340 disks D=20,
                         64 points, ratio 1.5, random sequential addition, 500 steps.
     cavity2048_free   : the same cavity without particles.
+    cavity2048_sparse : 2-D 2048^2, FP32, tau 0.8: the 128^2 layout tiled 16 x 16 (4096
+                        disks D=10 on a jittered grid of pitch 32, 32 points, ratio 1.5,
+                        area fraction 0.077).
     cavity8192_free   : 2-D 8192^2 FP32 cavity without particles (2.1 GB of PDFs, far
                         beyond the last-level cache: the collide-stream kernel against HBM).
     cavity256_free    : 3-D 256^3 FP32 cavity without particles.
@@ -89,7 +92,15 @@ def workload(name: str) -> dict:
                         ratio 2.0, BF16/FP16 PDF storage, 200 steps (FCC + deletion).
     cavity256_learned : 3-D 256^3, volume fraction 0.30: 2347 spheres D=16, learned
                         forcing, 200 steps (FCC + deletion).
+    <name>_btdf       : the workload <name> with the single-pass boundary-thickened direct
+                        forcing of Sec. 2.2: the 3-point kernel, shell thickness drs = 1.9
+                        lattice units, one forcing pass (the paper's setting for its
+                        particle-laden runs, Sec. 6.2).
     """
+    if name.endswith("_btdf"):
+        w = workload(name[:-len("_btdf")])
+        w["params"] = dict(w["params"], delta=1, drs=1.9, mdf_iters=1)
+        return w
     if name == "cavity128_f64":
         p = default_params(2, (128, 128), tau=0.8, storage="f64", mdf_iters=3)
         X = jittered_grid(seed=1, nx=4, ny=4, pitch=32.0, origin=16.0, jitter=5.0)
@@ -104,6 +115,12 @@ def workload(name: str) -> dict:
                 clearance=2.5)
         parts = dict(center=X, diameter=np.full(len(X), 20.0), density=np.full(len(X), 1.5),
                      n_markers=64)
+        return dict(params=p, particles=parts, steps=500)
+    if name == "cavity2048_sparse":
+        p = default_params(2, (2048, 2048), tau=0.8, storage="f32", mdf_iters=3)
+        X = jittered_grid(seed=6, nx=64, ny=64, pitch=32.0, origin=16.0, jitter=5.0)
+        parts = dict(center=X, diameter=np.full(len(X), 10.0), density=np.full(len(X), 1.5),
+                     n_markers=32)
         return dict(params=p, particles=parts, steps=500)
     if name == "cavity8192_free":
         return dict(params=default_params(2, (8192, 8192), tau=0.6, storage="f32", mdf_iters=3),

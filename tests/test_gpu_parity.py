@@ -96,17 +96,23 @@ def test_equilibrium_init_matches():
     _compare_fields(g, o, 1e-12, "eq-init")
 
 
-def _cfg1():
-    w = inputs.workload("cavity128_f64")
+def _cfg1(name="cavity128_f64"):
+    w = inputs.workload(name)
     return w["params"], w["particles"]
 
 
-@pytest.mark.parametrize("lds,band", [(1, None), (1, 1), (0, None)])
-def test_cavity128_f64_particles_100_steps(lds, band):
-    """The 2-D FP64 workload (16 disks, MDF-3): fields and particle states after 100
-    steps within 1e-12 relative, with the per-particle LDS kernels (band u* inside the
-    first interpolation, the 2-D default, or in its own pass) and the point-wise ones."""
-    p, parts = _cfg1()
+@pytest.mark.parametrize("name,lds,band", [("cavity128_f64", 1, None), ("cavity128_f64", 1, 1),
+                                           ("cavity128_f64", 0, None),
+                                           ("cavity128_f64_btdf", 1, None),
+                                           ("cavity128_f64_btdf", 1, 1),
+                                           ("cavity128_f64_btdf", 0, None)])
+def test_cavity128_f64_particles_100_steps(name, lds, band):
+    """The 2-D FP64 workload (16 disks): fields and particle states after 100 steps within
+    1e-12 relative, with the per-particle LDS kernels (band u* inside the first
+    interpolation, the 2-D default, or in its own pass) and the point-wise ones; with
+    MDF-3 and the 4-point kernel, and with the single-pass thickened shell (3-point
+    kernel, drs = 1.9)."""
+    p, parts = _cfg1(name)
     g, o = _pair(p)
     g.set_ibm_lds(lds)
     if band is not None:
@@ -179,16 +185,19 @@ def test_pairs_cells_bit_exact(dim, n, count):
     assert np.array_equal(g.pairs(), o.pairs())
 
 
-@pytest.mark.parametrize("lds,storage,tol,band", [(1, "f32", 1e-5, None), (1, "f32", 1e-5, 0),
-                                                  (0, "f32", 1e-5, None),
-                                                  (1, "f64", 1e-12, None), (1, "f64", 1e-12, 0)])
-def test_cavity3d_particles(lds, storage, tol, band):
-    """A 3-D cavity with spheres (MDF-3, 4-point delta), touching the walls' stencil
-    margins: fields within the storage tolerance; per-particle kernels with the band u*
-    in its own pass (the 3-D default) or inside the first interpolation, and the
-    point-wise kernels."""
+@pytest.mark.parametrize("lds,storage,tol,band,btdf", [
+    (1, "f32", 1e-5, None, False), (1, "f32", 1e-5, 0, False), (0, "f32", 1e-5, None, False),
+    (1, "f64", 1e-12, None, False), (1, "f64", 1e-12, 0, False),
+    (1, "f32", 1e-5, None, True), (0, "f32", 1e-5, None, True), (1, "f64", 1e-12, None, True)])
+def test_cavity3d_particles(lds, storage, tol, band, btdf):
+    """A 3-D cavity with spheres touching the walls' stencil margins, with MDF-3 and the
+    4-point kernel or the single-pass thickened shell (3-point kernel, drs = 1.9): fields
+    within the storage tolerance; per-particle kernels with the band u* in its own pass
+    (the 3-D default) or inside the first interpolation, and the point-wise kernels."""
     n = (48, 44, 40)
     p = inputs.default_params(3, n, tau=0.7, storage=storage, mdf_iters=3)
+    if btdf:
+        p.update(delta=1, drs=1.9, mdf_iters=1)
     X = inputs.jittered_grid(seed=9, nx=2, ny=2, pitch=20.0, origin=12.0, jitter=2.0, nz=2)
     g, o = _pair(p)
     g.set_ibm_lds(lds)
@@ -198,7 +207,7 @@ def test_cavity3d_particles(lds, storage, tol, band):
         s.add_particles(X, np.full(len(X), 10.0), np.full(len(X), 2.0), n_markers=314)
     g.step(30)
     o.step(30)
-    _compare_fields(g, o, tol, f"3D {storage} particles lds={lds} band={band}")
+    _compare_fields(g, o, tol, f"3D {storage} particles lds={lds} band={band} btdf={btdf}")
     pg, po = g.particles(), o.particles()
     assert rel_l2(pg["U"], po["U"]) < 10 * tol
     assert g.stats()["truncated"] == o.truncated()

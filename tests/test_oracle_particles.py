@@ -165,3 +165,58 @@ def test_hydrodynamic_reaction_balances_ib_force():
     _, _, f = s.fields()
     assert s.truncated() == 0
     assert np.allclose(-st["F_h"][:, :2].sum(0), f.sum(1), atol=1e-15, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim,D,nl", [(2, 10.0, 32), (3, 8.0, 200)])
+@pytest.mark.parametrize("drs", [1.0, 1.9, 2.6])
+def test_shell_volume_eq13(dim, D, nl, drs):
+    """Eq. 13: a point carries the shell volume drs * ds, with ds the arc length
+    pi D / N_L in 2-D and the area pi D^2 / N_L in 3-D, so the points of a particle
+    together carry drs times its perimeter or surface area."""
+    n = (40, 40) if dim == 2 else (24, 24, 24)
+    p = inputs.default_params(dim, n, tau=0.8, mdf_iters=1)
+    p["drs"] = drs
+    s = oracle.Sim(p)
+    c = [[n[0] / 2 + 0.3, n[1] / 2 - 0.2, (n[2] / 2 + 0.1) if dim == 3 else 0.0]]
+    s.add_particles(np.array(c), [D], [1.5], n_markers=nl)
+    dV = s.markers()["dV"]
+    ds = math.pi * D / nl if dim == 2 else math.pi * D * D / nl
+    assert len(dV) == nl
+    assert np.allclose(dV, drs * ds, rtol=1e-15)
+    area = math.pi * D if dim == 2 else 4 * math.pi * (D / 2) ** 2
+    assert abs(dV.sum() - drs * area) < 1e-12 * area
+
+
+@pytest.mark.parametrize("kind,drs", [(0, 2.6), (1, 1.9)])
+def test_thickened_shell_single_pass_slip(kind, drs):
+    """Sec. 2.2: with a shell thicker than one lattice unit (drs = 2.6 for the 4-point
+    kernel, 1.9 for the 3-point kernel) a single forcing pass leaves a slip far below the
+    one of the conventional single pass (drs = 1) on a resting cylinder in a uniform
+    stream."""
+    slips = []
+    for d in (1.0, drs):
+        p = inputs.default_params(2, (48, 48), tau=0.8, mdf_iters=1, gravity=(0, 0, 0))
+        p["delta"], p["drs"] = kind, d
+        s = oracle.Sim(p)
+        _, u = inputs.smooth_fields(0, 2, (48, 48, 1), amp_u=0.0, amp_p=0.0)
+        u[0] = 0.01
+        s.set_equilibrium(None, u)
+        s.add_particles(np.array([[24.0, 24.0, 0.0]]), [12.0], [1e6], n_markers=38)
+        s.step(1)
+        slips.append(s.slip_rms())
+    assert slips[1] < 0.15 * slips[0], slips
+
+
+def test_btdf_settling_is_stable_and_bounded():
+    """The paper's particle-laden setting (3-point kernel, drs = 1.9, one forcing pass) on
+    the 128^2 cavity settles stably, with velocities bounded by the free-fall value."""
+    w = inputs.workload("cavity128_f64_btdf")
+    s = oracle.Sim(w["params"])
+    parts = w["particles"]
+    s.add_particles(parts["center"], parts["diameter"], parts["density"],
+                    n_markers=parts["n_markers"])
+    s.step(300)
+    st = s.particles()
+    assert np.all(np.isfinite(st["U"]))
+    assert np.max(np.abs(st["U"])) < 300 * (1 - 1 / 1.5) * 1e-5
+    assert np.all(st["U"][:, 1] < 0)
