@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TIMING_EVERY = 10  # timed region: events on the dominant group's launches of every 10th step
 GROUPS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
-KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_band_ustar", "interp": "k_interp_lds",
+KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_ustar_all", "interp": "k_interp_lds",
                "spread": "k_spread_lds", "interior": "k_interior", "particle": "k_pairs"}
 
 
