@@ -204,6 +204,15 @@ constexpr int MAX_BOX_3D = 46;  // D <= 40 with a 4-point stencil
 // status bits
 constexpr int ST_CELL_OVERFLOW = 1, ST_PAIR_OVERFLOW = 2, ST_NAN = 4;
 
+// Once a runaway particle (|U| > 1 lattice unit per step, or NaN) has been flagged in the
+// device status word, the particle and IB kernels of later launches return at once: a
+// diverging run stops moving its bodies through the lattice, and iblbm_step reports
+// IBLBM_E_UNSTABLE when it returns.  The flag is set only inside the particle update,
+// which does not test it, so every other launch sees one value throughout.
+__device__ __forceinline__ bool halted(const int* status) {
+  return status != nullptr && (*status & ST_NAN) != 0;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (all enqueue on ctx->stream).
 void lbm_init_equilibrium(iblbm_ctx* c, const double* dp, const double* du);

@@ -52,6 +52,7 @@ struct PartView {
   const int* mown;
   const double* mr;  // nmk x 4
   const double* mdV;
+  const int* status;  // device status word (the kernels stop once a runaway is flagged)
 };
 
 __device__ __forceinline__ void marker_pos_vel(const PartView& P, int k, double* X, double* Ub,
@@ -158,7 +159,7 @@ __device__ __forceinline__ void point_result(const InterpArgs<C>& a, int k, cons
 
 template <int DIM, class C>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<C> a) {
-  if (a.cond && *a.cond == 0) return;
+  if ((a.cond && *a.cond == 0) || halted(a.P.status)) return;
   constexpr int G = DIM == 3 ? 64 : 16;
   int k = (blockIdx.x * blockDim.x + threadIdx.x) / G;
   int l = threadIdx.x & (G - 1);
@@ -203,7 +204,7 @@ struct SpreadArgs {
 // Eq. 11 with Eq. 13: f(x) += dF_k Phi(x - X_k) drs ds_k, with float atomics.
 template <int DIM, class C>
 __global__ __launch_bounds__(256) void k_spread(SpreadArgs<C> a) {
-  if (a.cond && *a.cond == 0) return;
+  if ((a.cond && *a.cond == 0) || halted(a.P.status)) return;
   constexpr int G = DIM == 3 ? 64 : 16;
   int k = (blockIdx.x * blockDim.x + threadIdx.x) / G;
   int l = threadIdx.x & (G - 1);
@@ -236,6 +237,7 @@ struct MarkArgs {
 // supports of its points in an LDS bitmap, then flags and lists each new segment once.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_mark(MarkArgs a) {
+  if (halted(a.P.status)) return;
   extern __shared__ uint32_t bits[];
   __shared__ int box[6];
   int p = blockIdx.x;
@@ -612,12 +614,14 @@ template <int DIM, class C>
 __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
+  // tested with the box below, so that its load overlaps the particle's
+  const bool stop = halted(a.P.status);
   int* wcnt = reinterpret_cast<int*>(smem_d);
   uint8_t* flag = reinterpret_cast<uint8_t*>(wcnt + 20);
   int p = blockIdx.x;
   double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  if (b.n > a.cap) return;  // the host sizes cap for the largest particle
+  if (stop || b.n > a.cap) return;  // the host sizes cap for the largest particle
   for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
   __syncthreads();
   int m0 = a.mstart[p], mc = a.mcount[p];
@@ -656,6 +660,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   using L = Lat<DIM>;
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
+  // tested with the box below, so that its load overlaps the particle's
+  const bool stop = halted(a.P.status);
   char* base = reinterpret_cast<char*>(smem_d);
   const InterpLayout Ly = interp_layout(DIM, sizeof(C), a.cap);
   C* ub = reinterpret_cast<C*>(base);
@@ -669,7 +675,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
   int m0 = a.mstart[p], mc = a.mcount[p];
   // the host sizes cap and the block for the largest particle
-  if (b.n > a.cap || mc > (int)blockDim.x) return;
+  if (stop || b.n > a.cap || mc > (int)blockDim.x) return;
   // this lane's point, loaded and weighted before the box is staged so that the
   // latencies overlap; with an accumulating pass also its force so far
   const int k = m0 + (int)threadIdx.x;
@@ -824,6 +830,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   using U = typename FX::U;
   extern __shared__ double smem_d[];
   if (a.cond && *a.cond == 0) return;
+  // tested with the box below, so that its load overlaps the particle's
+  const bool stop = halted(a.P.status);
   U* acc = reinterpret_cast<U*>(smem_d);
   double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_d) +
                                           spread_acc_bytes(DIM, sizeof(C), a.cap));
@@ -832,7 +840,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
   int m0 = a.mstart[p], mc = a.mcount[p];
   // the host sizes the box and the block for the largest particle
-  if (b.n > a.cap || mc > (int)blockDim.x) return;
+  if (stop || b.n > a.cap || mc > (int)blockDim.x) return;
   const int kind = a.g.kind, width = a.g.width;
   // this lane's point: 1-D weights, first support node, force times drs*ds (Eq. 13)
   const int kl = threadIdx.x;
@@ -954,7 +962,7 @@ __global__ __launch_bounds__(256) void k_band_prep(LdsArgs<typename Store<T>::C>
                                                     const int* seglist, const int* count, int nsegx) {
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
-  if (a.cond && *a.cond == 0) return;
+  if ((a.cond && *a.cond == 0) || halted(a.P.status)) return;
   int n = *count;
   int lane = threadIdx.x & (SEG - 1);
   T* slot[L::Q - 1];
@@ -1001,6 +1009,7 @@ PartView make_pview(const iblbm_ctx* c) {
   P.mown = c->mown;
   P.mr = c->mr;
   P.mdV = c->mdV;
+  P.status = c->dstatus;
   return P;
 }
 

@@ -180,6 +180,7 @@ struct InteriorArgs {
   double *P, *L;
   const C* ustar;  // u* of every node (FROMU), else computed from the PDFs
   int vd;
+  const int* status;  // device status word (the interior pass stops once a runaway is flagged)
 };
 
 // u* = sum_a e_a f_a / rho0 (Eq. 5) at every node, from the PDFs after streaming, in
@@ -216,6 +217,8 @@ __global__ __launch_bounds__(256) void k_ustar_all(InteriorArgs<typename Store<T
 // One workgroup per particle, FP64 accumulation and a fixed-order reduction.
 template <int DIM, class T, int PAR, int FROMU>
 __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>::C> a) {
+  // tested once the particle's loads are issued, so that the latencies overlap
+  const bool stop = halted(a.status);
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
   __shared__ double red[6][256];
@@ -229,6 +232,7 @@ __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>
   }
   int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
   int total = (wx > 0 && wy > 0 && wz > 0) ? wx * wy * wz : 0;
+  if (stop) return;
   T* slot[L::Q - 1];
   slots_of<DIM, T>(a.slot, slot);
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -370,6 +374,7 @@ struct RunInterior {
     a.L = Lm;
     a.ustar = (const C*)c->ustar;
     a.vd = c->vd;
+    a.status = c->dstatus;
     return a;
   }
   static void run(iblbm_ctx* c, double* P, double* Lm, bool from_u) {

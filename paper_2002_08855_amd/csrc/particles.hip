@@ -40,12 +40,16 @@ __device__ __forceinline__ int cell_coord(double x, double invh, int nc) {
 // and the run length, the head takes one atomic for the whole run, and the others
 // rank themselves by their distance from the head.
 __global__ void k_cells(PartArgs a) {
+  // tested after the position loads are issued, so that the latencies overlap
+  const bool stop = halted(a.status);
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool act = p < a.np;
   long long id = -1;
-  if (act) {
-    int c[3] = {0, 0, 0};
+  int c[3] = {0, 0, 0};
+  if (act)
     for (int d = 0; d < a.dim; d++) c[d] = cell_coord(a.X[3 * p + d], a.invh[d], a.nc[d]);
+  if (stop) return;
+  if (act) {
     for (int d = 0; d < 3; d++) a.cell_of[3 * p + d] = c[d];
     id = c[0] + (long long)a.nc[0] * (c[1] + (long long)a.nc[1] * c[2]);
   }
@@ -89,15 +93,20 @@ constexpr int MAXP = 32;
 // forces in ascending partner order (pairs first, then the wall images in face order)
 // and writes the partners j > i for the pair list.
 __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
+  // tested after the cell loads are issued, so that the latencies overlap
+  const bool stop = halted(a.status);
   __shared__ int cand[4][MAXP];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int i = blockIdx.x * 4 + wv;
   bool act = i < a.np;
   int ncand = 0;
   bool over = false;
+  int ci[3] = {0, 0, 0};
+  if (act)
+    for (int d = 0; d < 3; d++) ci[d] = a.cell_of[3 * i + d];
+  if (stop) return;
   if (act) {
     const double* Xi = a.X + 3 * i;
-    int ci[3] = {a.cell_of[3 * i], a.cell_of[3 * i + 1], a.cell_of[3 * i + 2]};
     int lo[3], w[3];
     for (int d = 0; d < 3; d++) {
       lo[d] = d < a.dim ? max(ci[d] - 2, 0) : 0;

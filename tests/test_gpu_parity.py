@@ -211,3 +211,27 @@ def test_cavity3d_particles(lds, storage, tol, band, btdf):
     pg, po = g.particles(), o.particles()
     assert rel_l2(pg["U"], po["U"]) < 10 * tol
     assert g.stats()["truncated"] == o.truncated()
+
+
+def test_runaway_particle_stops_the_particle_kernels():
+    """A particle launched at 1.5 lattice units per step is flagged as a runaway by the
+    particle update of its first step.  The IB and particle kernels of the later steps of
+    the same call return at once, so the point forces and the cells stay those of the
+    first step, and the call reports E_UNSTABLE; the context then refuses to step."""
+    b = _gpu()
+    p = inputs.default_params(2, (96, 96), tau=0.8, storage="f64", mdf_iters=2)
+    sims = []
+    for nsteps in (1, 4):
+        g = b.Sim(p)
+        g.add_particles([[48.0, 48.0, 0.0]], [10.0], [1.5], velocity=[[1.5, 0.0, 0.0]],
+                        n_markers=32)
+        with pytest.raises(b.IblbmError) as e:
+            g.step(nsteps)
+        assert "UNSTABLE" in str(e.value)
+        with pytest.raises(b.IblbmError):
+            g.step(1)
+        sims.append(g)
+    m1, m4 = (s.particles()["marker_F"] for s in sims)
+    assert np.any(m1 != 0) and np.array_equal(m1, m4)
+    (c1, d1), (c4, d4) = (s.cells() for s in sims)
+    assert np.array_equal(c1, c4) and np.array_equal(d1, d4)
