@@ -133,7 +133,11 @@ iblbm_status iblbm_add_particles(iblbm_ctx* ctx, int32_t n, const double* center
                                  int32_t markers_per_particle);
 
 /* Advance nsteps time steps; returns after the work is enqueued and the status word has
- * been read back (one device synchronisation per call). */
+ * been read back (one device synchronisation per call).  A particle faster than one
+ * lattice unit per step (or NaN) stops the particle and IB kernels of the remaining steps
+ * of the call; the call then returns IBLBM_E_UNSTABLE and the context refuses to step
+ * again (the getters still read the state).  Cell or pair lists that overflow their
+ * capacity return IBLBM_E_CAPACITY. */
 iblbm_status iblbm_step(iblbm_ctx* ctx, int32_t nsteps);
 
 /* p (Eq. 6) and u* (Eq. 5) of the current PDFs (N and dim*N values) and the IB force
