@@ -235,3 +235,56 @@ def test_runaway_particle_stops_the_particle_kernels():
     assert np.any(m1 != 0) and np.array_equal(m1, m4)
     (c1, d1), (c4, d4) = (s.cells() for s in sims)
     assert np.array_equal(c1, c4) and np.array_equal(d1, d4)
+
+
+def test_particles_added_in_two_batches():
+    """Particles added after the flow has started (the device arrays grow and keep the
+    first batch's state): fields and particle states after both batches have settled for
+    40 more steps, against the oracle doing the same, within the FP64 bar."""
+    p = inputs.default_params(2, (96, 80), tau=0.8, storage="f64", mdf_iters=3)
+    g, o = _pair(p)
+    first = np.array([[24.0, 30.0, 0.0], [70.0, 28.0, 0.0]])
+    second = np.array([[30.0, 58.0, 0.0], [64.0, 60.0, 0.0], [47.0, 44.0, 0.0]])
+    for s in (g, o):
+        s.add_particles(first, [10.0, 12.0], [1.5, 1.5], n_markers=32)
+        s.step(20)
+        s.add_particles(second, [10.0, 9.0, 8.0], [1.5, 2.0, 1.5], n_markers=30)
+        s.step(40)
+    _compare_fields(g, o, 1e-12, "two batches")
+    pg, po = g.particles(), o.particles()
+    assert pg["X"].shape == (5, 3)
+    for k in ("X", "U", "F_h"):
+        assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))
+    # the spin is a near-cancelling torque sum, six orders below U/R this early: compare it
+    # on the scale U/R of the translation
+    scale = np.abs(po["U"]).max() / 4.0
+    assert np.abs(pg["Omega"] - po["Omega"]).max() < 1e-11 * scale
+
+
+def test_large_sphere_takes_the_point_wise_kernels():
+    """A sphere whose support box exceeds the per-particle LDS limit (D = 36: 41^3 box
+    nodes) is handled by the point-wise kernels with no option set; FP64 parity."""
+    p = inputs.default_params(3, (52, 50, 48), tau=0.8, storage="f64", mdf_iters=2)
+    g, o = _pair(p)
+    for s in (g, o):
+        s.add_particles([[26.2, 24.7, 23.9]], [36.0], [1.5], n_markers=0)
+    g.step(8)
+    o.step(8)
+    _compare_fields(g, o, 1e-12, "large sphere")
+    assert rel_l2(g.particles()["U"], o.particles()["U"]) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["overlap", "outside", "wall_gap"])
+def test_add_particles_rejects_invalid_sets(case):
+    """Overlapping particles and surfaces outside the walls are refused with E_ARG, and
+    the context stays usable."""
+    b = _gpu()
+    g = b.Sim(inputs.default_params(2, (64, 64), tau=0.8, storage="f64", mdf_iters=1))
+    X = {"overlap": [[30.0, 30.0, 0.0], [37.0, 30.0, 0.0]],
+         "outside": [[3.0, 30.0, 0.0]],
+         "wall_gap": [[30.0, 59.0, 0.0]]}[case]
+    with pytest.raises(b.IblbmError) as e:
+        g.add_particles(X, [10.0] * len(X), [1.5] * len(X), n_markers=32)
+    assert "E_ARG" in str(e.value)
+    g.add_particles([[30.0, 30.0, 0.0]], [10.0], [1.5], n_markers=32)
+    g.step(2)
