@@ -48,6 +48,12 @@ typedef enum {
 typedef enum { IBLBM_F64 = 0, IBLBM_F32 = 1, IBLBM_BF16 = 2, IBLBM_F16 = 3 } iblbm_storage;
 typedef enum { IBLBM_DELTA_PESKIN4 = 0, IBLBM_DELTA_ROMA3 = 1 } iblbm_delta;
 typedef enum { IBLBM_FORCING_MDF = 0, IBLBM_FORCING_LEARNED = 1 } iblbm_forcing;
+/* Face conditions (Sec. 6.1).  WALL: half-way bounce-back with the face's wall_u.
+ * VELOCITY and PRESSURE: the non-equilibrium extrapolation of the paper's ref. [48] on the
+ * face's layer of nodes: f = f_eq(p_b, u_b) + (f - f_eq)(x_f) with x_f the next node
+ * inward; VELOCITY sets u_b = wall_u[face] and takes p_b from x_f, PRESSURE sets
+ * p_b = face_p[face] and takes u_b from x_f. */
+typedef enum { IBLBM_BC_WALL = 0, IBLBM_BC_VELOCITY = 1, IBLBM_BC_PRESSURE = 2 } iblbm_bc;
 
 /* Problem statement (Sec. 2 and Sec. 6.2): lattice, fluid, walls, forcing, particles. */
 typedef struct {
@@ -78,6 +84,10 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user); /* optional device allocator */
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
+  int32_t face_bc[6];     /* iblbm_bc per face -x,+x,-y,+y,-z,+z (0: walls everywhere).
+                           * Extrapolated faces must all lie on one non-periodic axis
+                           * with at least 3 nodes */
+  double face_p[6];       /* pressure of PRESSURE faces */
 } iblbm_config;
 
 #define IBLBM_NGROUPS 8

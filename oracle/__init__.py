@@ -39,7 +39,7 @@ class RefConfig(C.Structure):
         ("mdf_iters", C.c_int32), ("gravity", C.c_double * 3), ("zeta", C.c_double),
         ("eps_pp", C.c_double), ("E_pp", C.c_double), ("cell_h", C.c_double),
         ("streaming", C.c_int32), ("forcing", C.c_int32), ("slip_tol", C.c_double),
-        ("fallback_iters", C.c_int32),
+        ("fallback_iters", C.c_int32), ("face_bc", C.c_int32 * 6), ("face_p", C.c_double * 6),
     ]
 
 
@@ -253,6 +253,9 @@ def make_config(p: dict) -> RefConfig:
     c.forcing = int(p.get("forcing", 0))
     c.slip_tol = float(p.get("slip_tol", 1e30))
     c.fallback_iters = int(p.get("fallback_iters", 5))
+    for fce in range(6):
+        c.face_bc[fce] = int(p.get("face_bc", (0,) * 6)[fce])
+        c.face_p[fce] = float(p.get("face_p", (0.0,) * 6)[fce])
     return c
 
 

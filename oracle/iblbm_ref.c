@@ -390,9 +390,25 @@ static void* xcalloc(size_t n, size_t s) {
   return p;
 }
 
+/* Extrapolated faces (face_bc 1 or 2) must all lie on one non-periodic axis with at
+ * least 3 nodes, so that a boundary node's inward neighbour is never a boundary node. */
+static int faces_ok(const ref_config* cfg) {
+  int axis = -1;
+  for (int f = 0; f < 6; f++) {
+    if (cfg->face_bc[f] < 0 || cfg->face_bc[f] > 2) return 0;
+    if (cfg->face_bc[f] == 0) continue;
+    int a = f / 2;
+    if (a >= cfg->dim || cfg->periodic[a] || cfg->n[a] < 3) return 0;
+    if (axis >= 0 && axis != a) return 0;
+    axis = a;
+  }
+  return 1;
+}
+
 ref_ctx* ref_create(const ref_config* cfg) {
   if (cfg->dim != 2 && cfg->dim != 3) return NULL;
   if (!(cfg->tau > 0.5)) return NULL;
+  if (!faces_ok(cfg)) return NULL;
   ref_ctx* c = (ref_ctx*)xcalloc(1, sizeof(ref_ctx));
   c->cfg = *cfg;
   c->dim = cfg->dim;
@@ -876,6 +892,43 @@ static void stream_swap(ref_ctx* c) {
       }
 }
 
+/* Sec. 6.1 boundaries by non-equilibrium extrapolation (the paper's ref. [48]): on the
+ * node layer of an inflow or outflow face, after streaming, every population becomes
+ * f_eq(p_b, u_b) + (f - f_eq(p_f, u_f)) at the next node inward x_f.  A velocity face
+ * prescribes u_b (its wall_u) and takes p_b = p_f; a pressure face prescribes p_b (its
+ * face_p) and takes u_b = u_f.  The inward nodes are never boundary nodes (faces_ok), so
+ * the nodes can be updated in any order. */
+static void apply_face_bc(ref_ctx* c) {
+  long N = c->N;
+  int q = c->q, d = c->dim;
+  const int* n = c->cfg.n;
+  for (int face = 0; face < 6; face++) {
+    int kind = c->cfg.face_bc[face];
+    if (kind == 0) continue;
+    int ax = face / 2, hi = face % 2;
+    long layer = hi ? n[ax] - 1 : 0, step = hi ? -1 : 1;
+    for (long z = 0; z < n[2]; z++)
+      for (long y = 0; y < n[1]; y++)
+        for (long x = 0; x < n[0]; x++) {
+          long cb[3] = {x, y, z};
+          if (cb[ax] != layer) continue;
+          long cf[3] = {x, y, z};
+          cf[ax] += step;
+          long ib = cb[0] + n[0] * (cb[1] + (long)n[1] * cb[2]);
+          long jf = cf[0] + n[0] * (cf[1] + (long)n[1] * cf[2]);
+          double ff[19], pf, uf[3], pb, ub[3], eqb[19], eqf[19];
+          ff[0] = 0.0;
+          for (int a = 1; a < q; a++) ff[a] = c->f[(a - 1) * N + jf];
+          ref_macro(d, c->cfg.rho0, ff, &pf, uf);
+          for (int k = 0; k < 3; k++) ub[k] = kind == 1 ? (k < d ? c->cfg.wall_u[face][k] : 0.0) : uf[k];
+          pb = kind == 1 ? pf : c->cfg.face_p[face];
+          ref_feq(d, c->cfg.rho0, pb, ub, eqb);
+          ref_feq(d, c->cfg.rho0, pf, uf, eqf);
+          for (int a = 1; a < q; a++) c->f[(a - 1) * N + ib] = eqb[a] + (ff[a] - eqf[a]);
+        }
+  }
+}
+
 static void particle_loads(ref_ctx* c) {
   /* F_h = -sum F_k dV_k and T_h = -sum r_k x F_k dV_k (reaction of the IB force) */
   for (int p = 0; p < c->np; p++) {
@@ -1048,6 +1101,7 @@ int32_t ref_step(ref_ctx* c, int32_t nsteps) {
       collide(c, c->ft);
       stream_two_array(c, c->ft, c->f);
     }
+    apply_face_bc(c);
     /* (5) particles */
     if (c->np > 0) {
       /* momentum of the fluid inside each particle after streaming (u* of the new PDFs) */

@@ -42,6 +42,9 @@ typedef struct {
   int32_t forcing;        /* 0: multi-direct forcing, 1: learned force + one correction pass */
   double slip_tol;        /* learned forcing: fall back to MDF when the slip rms exceeds it */
   int32_t fallback_iters; /* MDF passes used by the fallback */
+  int32_t face_bc[6];     /* per face: 0 wall; 1 velocity (u = wall_u), 2 pressure (p =
+                           * face_p) by non-equilibrium extrapolation (Sec. 6.1) */
+  double face_p[6];
 } ref_config;
 
 /* ---- pure functions (pins and tests) ---------------------------------- */

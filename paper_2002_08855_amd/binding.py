@@ -36,6 +36,7 @@ class Config(C.Structure):
         ("cell_h", C.c_double), ("forcing", C.c_int32), ("slip_tol", C.c_double),
         ("fallback_iters", C.c_int32), ("stats_every", C.c_int32), ("stream", C.c_void_p),
         ("dev_alloc", _ALLOC), ("dev_free", _FREE), ("alloc_user", C.c_void_p),
+        ("face_bc", C.c_int32 * 6), ("face_p", C.c_double * 6),
     ]
 
 
@@ -160,6 +161,9 @@ def make_config(p: dict, stream=None, use_torch_alloc=True):
     c.slip_tol = float(p.get("slip_tol", 1e30))
     c.fallback_iters = int(p.get("fallback_iters", 5))
     c.stats_every = int(p.get("stats_every", 0))
+    for fce in range(6):
+        c.face_bc[fce] = int(p.get("face_bc", (0,) * 6)[fce])
+        c.face_p[fce] = float(p.get("face_p", (0.0,) * 6)[fce])
     keep = []
     if stream is not None:
         c.stream = stream

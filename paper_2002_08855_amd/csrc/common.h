@@ -220,6 +220,7 @@ void lbm_set_pdfs(iblbm_ctx* c, const double* df);
 void lbm_get_pdfs(iblbm_ctx* c, double* df);
 void lbm_get_fields(iblbm_ctx* c, double* dp, double* du, double* dforce);
 void lbm_collide_stream(iblbm_ctx* c);
+void lbm_face_bc(iblbm_ctx* c);  // after the parity flip: extrapolated faces for the next step
 void ibm_band(iblbm_ctx* c);
 bool ibm_uses_lds(const iblbm_ctx* c);
 void ibm_interp(iblbm_ctx* c, int first_pass, int mode);

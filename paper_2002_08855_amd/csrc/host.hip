@@ -200,8 +200,9 @@ void enqueue_step(iblbm_ctx* c) {
   }
   tbegin(c, IBLBM_T_COLLIDE);
   lbm_collide_stream(c);
-  tend(c);
   c->parity ^= 1;
+  lbm_face_bc(c);
+  tend(c);
   c->ustar_valid = false;
   if (parts) {
     // u* of the new PDFs at every node for the interior momentum and the next step's
@@ -319,6 +320,20 @@ iblbm_status iblbm_create(const iblbm_config* cfg, iblbm_ctx** out) {
   }
   int q = cfg->dim == 2 ? 9 : 19;
   if ((long long)(q - 1) * N >= (1LL << 31)) return IBLBM_E_ARG;
+  // extrapolated faces: all on one non-periodic axis of at least 3 nodes, so that no
+  // face node is the inward neighbour of another
+  {
+    int axis = -1;
+    for (int f = 0; f < 6; f++) {
+      const int k = cfg->face_bc[f];
+      if (k < IBLBM_BC_WALL || k > IBLBM_BC_PRESSURE) return IBLBM_E_ARG;
+      if (k == IBLBM_BC_WALL) continue;
+      const int a = f / 2;
+      if (a >= cfg->dim || cfg->periodic[a] || cfg->n[a] < 3) return IBLBM_E_ARG;
+      if (axis >= 0 && axis != a) return IBLBM_E_ARG;
+      axis = a;
+    }
+  }
   iblbm_ctx* c = new iblbm_ctx();
   c->cfg = *cfg;
   c->dim = cfg->dim;

@@ -171,6 +171,74 @@ __global__ void k_scatter(ScatterArgs<typename Store<T>::C> a) {
   }
 }
 
+// Inflow and outflow faces (Sec. 6.1) by non-equilibrium extrapolation, after the
+// collide-stream kernel: on the face's node layer, the populations the next step reads
+// become f_eq(p_b, u_b) + (f - f_eq(p_f, u_f)) at the next node inward x_f (Eq. 4 for
+// f_eq, Eqs. 5-6 for p_f and u_f).  A velocity face sets u_b and takes p_b = p_f; a
+// pressure face sets p_b and takes u_b = u_f.  One lane per face node.  The lanes write
+// only the links into face nodes and read only links into inward nodes, which are never
+// face nodes (the extrapolated faces share one axis of at least 3 nodes), so the update
+// is race free.
+template <class C>
+struct FaceArgs {
+  Geo<C> g;
+  SlotPtrs slot;
+  C inv_s, rho0;
+  int face, kind;  // kind 1: velocity (ub), 2: pressure (pb)
+  C ub[3], pb;
+};
+
+template <int DIM, class C>
+__device__ __forceinline__ C eq_pressure(C S, const C* u, C rho0) {
+  const C w0 = C(Lat<DIM>::w[0]);
+  return (C(1) / C(3)) / (C(1) - w0) * (S - rho0 * w0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * C(1.5));
+}
+
+template <int DIM, class C>
+__device__ __forceinline__ C feq_dir(int d, C p, const C* u, C rho0) {
+  using L = Lat<DIM>;
+  const C eu = L::ex[d] * u[0] + L::ey[d] * u[1] + (DIM == 3 ? L::ez[d] * u[2] : C(0));
+  const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return C(L::w[d]) * (C(3) * p + rho0 * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+}
+
+template <int DIM, class T, int PN>
+__global__ __launch_bounds__(256) void k_face_bc(FaceArgs<typename Store<T>::C> a) {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  const int ax = a.face / 2, hi = a.face & 1;
+  const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;  // the face's own axes
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)a.g.n[o0] * a.g.n[o1]) return;
+  int cb[3], cf[3];
+  cb[o0] = (int)(k % a.g.n[o0]);
+  cb[o1] = (int)(k / a.g.n[o0]);
+  cb[ax] = hi ? a.g.n[ax] - 1 : 0;
+  for (int d = 0; d < 3; d++) cf[d] = cb[d];
+  cf[ax] += hi ? -1 : 1;
+  const int ib = cb[0] + a.g.n[0] * (cb[1] + a.g.n[1] * cb[2]);
+  const int jf = cf[0] + a.g.n[0] * (cf[1] + a.g.n[1] * cf[2]);
+  T* slot[L::Q - 1];
+  slots_of<DIM, T>(a.slot, slot);
+  C f[L::Q];
+  load_all<DIM, T, PN>(slot, a.g, cf[0], cf[1], cf[2], jf, a.inv_s, f);
+  C S, uf[3];
+  moments<DIM, C>(f, a.rho0, S, uf);
+  const C pf = eq_pressure<DIM, C>(S, uf, a.rho0);
+  C ub[3] = {uf[0], uf[1], uf[2]};
+  C pb = a.pb;
+  if (a.kind == 1) {
+    for (int d = 0; d < 3; d++) ub[d] = a.ub[d];
+    pb = pf;
+  }
+  C fb[L::Q];
+  fb[0] = C(0);
+#pragma unroll
+  for (int d = 1; d < L::Q; d++)
+    fb[d] = feq_dir<DIM, C>(d, pb, ub, a.rho0) + (f[d] - feq_dir<DIM, C>(d, pf, uf, a.rho0));
+  set_incoming_all<DIM, T, PN>(slot, a.g, cb[0], cb[1], cb[2], ib, a.inv_s, fb);
+}
+
 template <class C>
 struct InteriorArgs {
   Geo<C> g;
@@ -389,6 +457,34 @@ struct RunInterior {
 };
 
 template <int DIM, class T>
+struct RunFaceBc {
+  static void run(iblbm_ctx* c) {
+    using C = typename Store<T>::C;
+    for (int face = 0; face < 6; face++) {
+      const int kind = c->cfg.face_bc[face];
+      if (kind == 0) continue;
+      FaceArgs<C> a;
+      a.g = make_geo<C>(c);
+      a.slot = make_slots(c);
+      a.inv_s = inv_scale<T>(c);
+      a.rho0 = C(c->cfg.rho0);
+      a.face = face;
+      a.kind = kind;
+      for (int d = 0; d < 3; d++) a.ub[d] = d < DIM ? C(c->cfg.wall_u[face][d]) : C(0);
+      a.pb = C(c->cfg.face_p[face]);
+      const int ax = face / 2;
+      const long long nodes = c->N / c->cfg.n[ax];
+      const unsigned blocks = (unsigned)((nodes + 255) / 256);
+      // the populations the next step reads, in its parity's layout
+      if (c->parity == 0)
+        hipLaunchKernelGGL((k_face_bc<DIM, T, 0>), dim3(blocks), dim3(256), 0, c->stream, a);
+      else
+        hipLaunchKernelGGL((k_face_bc<DIM, T, 1>), dim3(blocks), dim3(256), 0, c->stream, a);
+    }
+  }
+};
+
+template <int DIM, class T>
 struct RunUstarAll {
   static void run(iblbm_ctx* c) {
     auto a = RunInterior<DIM, T>::args(c, nullptr, nullptr);
@@ -412,6 +508,13 @@ void lbm_ustar_all(iblbm_ctx* c) {
 }
 
 void lbm_collide_stream(iblbm_ctx* c) { dispatch<RunCollide>(c); }
+void lbm_face_bc(iblbm_ctx* c) {
+  for (int f = 0; f < 6; f++)
+    if (c->cfg.face_bc[f] != 0) {
+      dispatch<RunFaceBc>(c);
+      return;
+    }
+}
 void lbm_get_fields(iblbm_ctx* c, double* p, double* u, double* force) {
   dispatch<RunGather>(c, p, u, force, (double*)nullptr);
 }

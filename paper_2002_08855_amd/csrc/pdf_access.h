@@ -108,6 +108,42 @@ struct StoreDir {
   }
 };
 
+// Set the value that LoadDir<DIM, T, PAR, A> reads at node (x, y, z): its own slot (even
+// layout), the opposite slot of the upstream neighbour, or, for a link from outside a
+// wall, its own slot less the wall term that the load adds back.
+template <int DIM, class T, int PAR, int A>
+struct SetIncomingDir {
+  using C = typename Store<T>::C;
+  using L = Lat<DIM>;
+  __device__ __forceinline__ static void run(T* const* slot, const Geo<C>& g, int x, int y, int z,
+                                             int i, C v, C inv_s) {
+    if (PAR == 0) {
+      st_pdf<false>(&slot[A - 1][i], Store<T>::save(v, inv_s));
+      return;
+    }
+    bool wall;
+    int face;
+    int j = neighbour<-L::ex[A], -L::ey[A], -L::ez[A], C>(g, x, y, z, wall, face);
+    constexpr int O = opp_dir(A, L::H);
+    if (!wall)
+      st_pdf<false>(&slot[O - 1][j], Store<T>::save(v, inv_s));
+    else
+      st_pdf<false>(&slot[A - 1][i], Store<T>::save(v - g.wt[A][face], inv_s));
+  }
+};
+
+// The populations a step of parity PAR reads at node (x, y, z) become f[1..q-1].
+template <int DIM, class T, int PAR, int A = 1>
+__device__ __forceinline__ void set_incoming_all(T* const* slot, const Geo<typename Store<T>::C>& g,
+                                                 int x, int y, int z, int i,
+                                                 typename Store<T>::C inv_s,
+                                                 const typename Store<T>::C* f) {
+  if constexpr (A < Lat<DIM>::Q) {
+    SetIncomingDir<DIM, T, PAR, A>::run(slot, g, x, y, z, i, f[A], inv_s);
+    set_incoming_all<DIM, T, PAR, A + 1>(slot, g, x, y, z, i, inv_s, f);
+  }
+}
+
 template <int DIM, class T, int PAR, int A = 1>
 __device__ __forceinline__ void load_all(T* const* slot, const Geo<typename Store<T>::C>& g, int x,
                                          int y, int z, int i, typename Store<T>::C inv_s,

@@ -288,3 +288,59 @@ def test_add_particles_rejects_invalid_sets(case):
     assert "E_ARG" in str(e.value)
     g.add_particles([[30.0, 30.0, 0.0]], [10.0], [1.5], n_markers=32)
     g.step(2)
+
+
+FACE_CASES = [
+    # dim, n, periodic, face_bc, storage, steps, tol
+    (2, (30, 41), (0, 0, 0), (0, 0, 1, 2, 0, 0), "f64", 100, 1e-12),
+    (2, (37, 26), (0, 1, 0), (2, 1, 0, 0, 0, 0), "f64", 100, 1e-12),
+    (3, (14, 19, 12), (1, 0, 0), (0, 0, 1, 2, 0, 0), "f64", 60, 1e-12),
+    (3, (12, 13, 17), (0, 0, 0), (0, 0, 0, 0, 1, 2), "f64", 60, 1e-12),
+    (2, (64, 90), (0, 0, 0), (0, 0, 1, 2, 0, 0), "f32", 100, 1e-5),
+    (3, (20, 24, 16), (0, 0, 1), (0, 0, 1, 2, 0, 0), "f32", 60, 1e-5),
+]
+
+
+@pytest.mark.parametrize("dim,n,per,faces,storage,steps,tol", FACE_CASES)
+def test_inflow_outflow_faces(dim, n, per, faces, storage, steps, tol):
+    """Velocity inflow and pressure outflow faces by non-equilibrium extrapolation
+    (Sec. 6.1) on each axis, from a smooth random state, over both step parities."""
+    p = inputs.default_params(dim, n, tau=0.7, storage=storage, mdf_iters=0, periodic=per)
+    p["face_bc"] = faces
+    wall = [[0.0, 0.0, 0.0] for _ in range(6)]
+    pres = [0.0] * 6
+    for f, k in enumerate(faces):
+        if k == 1:
+            wall[f] = [0.004, 0.02, -0.003][:dim] + [0.0] * (3 - dim)
+            wall[f][f // 2] = 0.03 if f % 2 == 0 else -0.03
+        elif k == 2:
+            pres[f] = 0.002 * (f + 1)
+    p["wall_u"], p["face_p"] = wall, pres
+    g, o = _pair(p)
+    nn = tuple(n) + (1,) * (3 - dim)
+    pp, uu = inputs.smooth_fields(7, dim, nn, amp_u=0.02, amp_p=0.01)
+    g.set_equilibrium(pp, uu)
+    o.set_equilibrium(pp, uu)
+    g.step(steps)
+    o.step(steps)
+    _compare_fields(g, o, tol, f"faces {faces} {storage}")
+
+
+def test_inflow_outflow_channel_with_particles():
+    """Disks settling in a channel between an inflow and an outflow face (the paper's
+    boundary method with the IB coupling): fields and particle states after 100 steps."""
+    p = inputs.default_params(2, (64, 96), tau=0.8, storage="f64", mdf_iters=3)
+    p["face_bc"] = (0, 0, 1, 2, 0, 0)
+    wall = [[0.0, 0.0, 0.0] for _ in range(6)]
+    wall[2] = [0.0, 0.002, 0.0]
+    p["wall_u"] = wall
+    g, o = _pair(p)
+    X = np.array([[20.0, 40.0, 0.0], [44.0, 52.0, 0.0], [31.0, 70.0, 0.0]])
+    for s in (g, o):
+        s.add_particles(X, [10.0, 12.0, 9.0], [1.5, 1.5, 1.5], n_markers=32)
+    g.step(100)
+    o.step(100)
+    _compare_fields(g, o, 1e-12, "channel with particles")
+    pg, po = g.particles(), o.particles()
+    for k in ("X", "U", "F_h"):
+        assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))

@@ -132,3 +132,69 @@ def test_swap_equals_two_array(dim, n, per):
     a.step(7)
     b.step(7)
     assert np.array_equal(a.get_pdfs(), b.get_pdfs())
+
+
+def _channel(dim, n, tau, U, periodic=(0, 0, 0), u_in=None):
+    """Inflow (velocity, -y face) and outflow (pressure 0, +y face) by non-equilibrium
+    extrapolation (Sec. 6.1); the other faces as given."""
+    p = inputs.default_params(dim, n, tau=tau, storage="f64", mdf_iters=0, periodic=periodic)
+    p["face_bc"] = (0, 0, 1, 2, 0, 0)
+    wall = [[0.0, 0.0, 0.0] for _ in range(6)]
+    wall[2] = list(u_in) if u_in is not None else [0.0, U, 0.0]
+    p["wall_u"] = wall
+    return p
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniform_stream_is_a_fixed_point_of_the_extrapolated_faces(dim):
+    """A uniform stream at zero pressure between a velocity inlet and a pressure outlet
+    (periodic across) is an equilibrium state with no gradients: the step must leave it
+    unchanged."""
+    n = (24, 40, 1) if dim == 2 else (10, 14, 8)
+    per = (1, 0, 0) if dim == 2 else (1, 0, 1)
+    u_in = [0.01, 0.03, 0.0] if dim == 2 else [0.01, 0.03, -0.02]
+    p = _channel(dim, n[:dim], 0.7, 0.0, periodic=per, u_in=u_in)
+    s = oracle.Sim(p)
+    _, u = inputs.smooth_fields(0, dim, n, amp_u=0.0, amp_p=0.0)
+    for a in range(dim):
+        u[a] = u_in[a]
+    s.set_equilibrium(None, u)
+    f0 = s.get_pdfs().copy()
+    s.step(50)
+    assert np.abs(s.get_pdfs() - f0).max() < 1e-15
+
+
+def test_channel_with_inflow_and_outflow_develops_poiseuille_flow():
+    """Walls across x, inflow at the bottom and outflow at the top (Sec. 6.1): the steady
+    flow has the same flux through every row, a uniform pressure across the section, the
+    parabolic profile of the mean velocity ubar, and the Poiseuille pressure gradient
+    dp/dy = -12 nu rho0 ubar / H^2 with H the wall distance (walls half-way outside the
+    first and last nodes)."""
+    nx, ny, tau, U = 16, 96, 0.8, 0.01
+    s = oracle.Sim(_channel(2, (nx, ny), tau, U))
+    _, u = inputs.smooth_fields(0, 2, (nx, ny, 1), amp_u=0.0, amp_p=0.0)
+    u[1] = U
+    s.set_equilibrium(None, u)
+    s.step(6000)
+    p, u, _ = s.fields()
+    uy = u[1].reshape(ny, nx)
+    pr = p.reshape(ny, nx)
+    flux = uy[1:-1].sum(1)
+    assert np.abs(flux - flux.mean()).max() < 1e-6 * flux.mean()
+    ubar = uy[48].mean()
+    assert 0.9 * U < ubar < 1.01 * U
+    H, nu = float(nx), (tau - 0.5) / 3.0
+    x = np.arange(nx) + 0.5
+    par = 1.5 * ubar * (1.0 - ((x - H / 2) / (H / 2)) ** 2)
+    assert np.abs(uy[48] - par).max() < 5e-3 * par.max()
+    assert pr[48].std() < 1e-9 * abs(pr[48].mean()) + 1e-12
+    dpdy = (pr[60].mean() - pr[36].mean()) / 24.0
+    assert abs(dpdy / (-12.0 * nu * ubar / H ** 2) - 1.0) < 5e-3
+
+
+def test_extrapolated_faces_must_share_one_axis():
+    """Inflow and outflow faces on two different axes are refused."""
+    p = _channel(2, (20, 20), 0.8, 0.01)
+    p["face_bc"] = (2, 0, 1, 0, 0, 0)
+    with pytest.raises(ValueError):
+        oracle.Sim(p)
