@@ -281,6 +281,38 @@ def run_forms(args):
     return forms
 
 
+SWEEP = {2: [40, 100, 200, 400, 1000, 2000, 4000, 8192], 3: [40, 80, 128, 160, 210, 256, 384, 480]}
+
+
+def run_sweep(args):
+    """The particle-free channel of Sec. 6.1 (inflow and outflow faces by non-equilibrium
+    extrapolation) at the paper's domain sizes and beyond, FP32: MLUPS against the number
+    of nodes, and the collide-stream rate against the HBM peak."""
+    import numpy as np
+    import torch
+
+    from paper_2002_08855_amd import binding, inputs
+
+    rows = []
+    for dim in (2, 3):
+        q = 9 if dim == 2 else 19
+        for n in SWEEP[dim]:
+            w = inputs.workload(f"channel{dim}d_{n}")
+            p = w["params"]
+            N = int(np.prod(p["n"]))
+            sim = binding.Sim(p)
+            steps = int(max(20, min(2000, 4e9 / N)))
+            r = _timed(sim, N, steps, 10)
+            bytes_per_node = 2 * (q - 1) * 4
+            gbs = r["value"] * 1e6 * bytes_per_node / 1e9
+            rows.append({"dim": dim, "n": n, "nodes": N, "mlups": r["value"], "ms_per_step": r["ms_per_step"],
+                         "steps": steps, "step_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del sim
+            torch.cuda.empty_cache()
+    return {"sweep": "channel (Sec. 6.1), FP32, whole step", "unit": "MLUPS", "rows": rows}
+
+
 def cpu_baseline(w, args):
     """The CPU oracle (FP64, OpenMP over lattice loops) on a bounded sample of the same
     workload: the same lattice and particles, a few steps."""
@@ -322,11 +354,17 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and learned-forcing forms")
     ap.add_argument("--form-steps", type=int, default=20)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline line: MLUPS of the particle-free channel "
+                         "(inflow/outflow faces) against the domain size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the IB-LBM step runs on one GPU; --gpus above 1 is not "
                                    "supported (the multi-GPU slab decomposition is not built)"}))
         sys.exit(2)
+    if args.sweep:
+        print(json.dumps(run_sweep(args)), flush=True)
+        return
     out = run(args)
     print(json.dumps(out), flush=True)
 

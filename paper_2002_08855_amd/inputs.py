@@ -92,11 +92,24 @@ def workload(name: str) -> dict:
                         ratio 2.0, BF16/FP16 PDF storage, 200 steps (FCC + deletion).
     cavity256_learned : 3-D 256^3, volume fraction 0.30: 2347 spheres D=16, learned
                         forcing, 200 steps (FCC + deletion).
+    channel2d_<n> / channel3d_<n>: the particle-free flow of Sec. 6.1 on n^2 / n^3 nodes,
+                        FP32, tau 0.6: inflow at the bottom (uniform 0.01 lattice units
+                        per step) and outflow at the top (pressure 0) by non-equilibrium
+                        extrapolation, bounce-back walls on the other faces.
     <name>_btdf       : the workload <name> with the single-pass boundary-thickened direct
                         forcing of Sec. 2.2: the 3-point kernel, shell thickness drs = 1.9
                         lattice units, one forcing pass (the paper's setting for its
                         particle-laden runs, Sec. 6.2).
     """
+    if name.startswith("channel2d_") or name.startswith("channel3d_"):
+        dim = 2 if name.startswith("channel2d_") else 3
+        n = int(name.split("_")[1])
+        p = default_params(dim, (n,) * dim, tau=0.6, storage="f32", mdf_iters=0)
+        p["face_bc"] = (0, 0, 1, 2, 0, 0)
+        wall = [[0.0, 0.0, 0.0] for _ in range(6)]
+        wall[2] = [0.0, 0.01, 0.0]
+        p["wall_u"] = wall
+        return dict(params=p, particles=None, steps=200)
     if name.endswith("_btdf"):
         w = workload(name[:-len("_btdf")])
         w["params"] = dict(w["params"], delta=1, drs=1.9, mdf_iters=1)
