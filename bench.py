@@ -313,6 +313,45 @@ def run_sweep(args):
     return {"sweep": "channel (Sec. 6.1), FP32, whole step", "unit": "MLUPS", "rows": rows}
 
 
+NP_SWEEP = {2: [1, 10, 100, 1000, 5000, 10000], 3: [1, 10, 100, 300, 600]}
+
+
+def run_np_sweep(args):
+    """The particle-count series of Table 7 (Sec. 6.2.1): whole-step MLUPS and the time of
+    each kernel group per step as the number of particles grows in a fixed lattice
+    (2048^2 with D = 16, 150^3 with D = 12; FP32, MDF-3)."""
+    import numpy as np
+    import torch
+
+    from paper_2002_08855_amd import binding, inputs
+
+    rows = []
+    for dim in (2, 3):
+        for count in NP_SWEEP[dim]:
+            w = inputs.workload(f"np{dim}d_{count}")
+            p, parts = w["params"], w["particles"]
+            N = int(np.prod(p["n"]))
+            sim = _sim(binding, p, parts)
+            steps = 100 if dim == 2 else 50
+            r = _timed(sim, N, steps, 5)
+            sim.set_stats_every(0)
+            sim.set_timing(1)
+            sim.reset_stats()
+            sim.step(20)
+            st = sim.stats()
+            sim.set_timing(0)
+            groups = {g: round(st["time_ms"][g] / 20, 5) for g in GROUPS if st["launches"][g]}
+            np_, nmk = sim.counts()
+            rows.append({"dim": dim, "particles": np_, "points": nmk,
+                         "mesh_ratio": round(nmk / N, 6), "mlups": r["value"],
+                         "ms_per_step": r["ms_per_step"], "slip_rms": r["slip_rms"],
+                         "kernel_ms_per_step": groups})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del sim
+            torch.cuda.empty_cache()
+    return {"sweep": "particle count (Table 7), FP32, MDF-3", "unit": "MLUPS", "rows": rows}
+
+
 def cpu_baseline(w, args):
     """The CPU oracle (FP64, OpenMP over lattice loops) on a bounded sample of the same
     workload: the same lattice and particles, a few steps."""
@@ -357,6 +396,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line: MLUPS of the particle-free channel "
                          "(inflow/outflow faces) against the domain size")
+    ap.add_argument("--np-sweep", action="store_true",
+                    help="instead of the headline line: MLUPS and kernel-group times against "
+                         "the number of particles (Table 7)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the IB-LBM step runs on one GPU; --gpus above 1 is not "
@@ -364,6 +406,9 @@ def main():
         sys.exit(2)
     if args.sweep:
         print(json.dumps(run_sweep(args)), flush=True)
+        return
+    if args.np_sweep:
+        print(json.dumps(run_np_sweep(args)), flush=True)
         return
     out = run(args)
     print(json.dumps(out), flush=True)

@@ -92,6 +92,10 @@ def workload(name: str) -> dict:
                         ratio 2.0, BF16/FP16 PDF storage, 200 steps (FCC + deletion).
     cavity256_learned : 3-D 256^3, volume fraction 0.30: 2347 spheres D=16, learned
                         forcing, 200 steps (FCC + deletion).
+    np2d_<Np> / np3d_<Np>: the particle-count series of Table 7: 2048^2 FP32 with Np
+                        disks D=16 (Np <= 10^4), 150^3 FP32 with Np spheres D=12 (Np <= 600),
+                        round(pi D) / round(pi D^2) points, ratio 1.5, MDF-3, on a thinned
+                        square or cubic lattice (pitch 20 / 15, jitter 1).
     channel2d_<n> / channel3d_<n>: the particle-free flow of Sec. 6.1 on n^2 / n^3 nodes,
                         FP32, tau 0.6: inflow at the bottom (uniform 0.01 lattice units
                         per step) and outflow at the top (pressure 0) by non-equilibrium
@@ -101,6 +105,24 @@ def workload(name: str) -> dict:
                         lattice units, one forcing pass (the paper's setting for its
                         particle-laden runs, Sec. 6.2).
     """
+    if name.startswith("np2d_") or name.startswith("np3d_"):
+        # the particle-count series of Table 7 (Sec. 6.2.1): 2048^2 with D = 16 up to 10^4
+        # disks, 150^3 with D = 12 up to 600 spheres; plain MDF-3, density ratio 1.5
+        dim = 2 if name.startswith("np2d_") else 3
+        count = int(name.split("_")[1])
+        if dim == 2:
+            p = default_params(2, (2048, 2048), tau=0.6, storage="f32", mdf_iters=3)
+            X = lattice_pick(seed=7, dim=2, n=(2048, 2048), count=count, diameter=16.0,
+                             pitch=20.0, clearance=2.5, jitter=1.0)
+            D = 16.0
+        else:
+            p = default_params(3, (150, 150, 150), tau=0.7, storage="f32", mdf_iters=3)
+            X = lattice_pick(seed=8, dim=3, n=(150, 150, 150), count=count, diameter=12.0,
+                             pitch=15.0, clearance=2.5, jitter=1.0)
+            D = 12.0
+        parts = dict(center=X, diameter=np.full(count, D), density=np.full(count, 1.5),
+                     n_markers=0)
+        return dict(params=p, particles=parts, steps=200)
     if name.startswith("channel2d_") or name.startswith("channel3d_"):
         dim = 2 if name.startswith("channel2d_") else 3
         n = int(name.split("_")[1])
@@ -184,6 +206,27 @@ def jittered_grid(seed, nx, ny, pitch, origin, jitter, nz=None):
     X = np.array(pts, dtype=np.float64)
     dims = 2 if nz is None else 3
     X[:, :dims] += rng.uniform(len(X) * dims, -jitter, jitter).reshape(len(X), dims)
+    return X
+
+
+def lattice_pick(seed, dim, n, count, diameter, pitch, clearance, jitter):
+    """`count` sites drawn without replacement (seeded) from a square or cubic lattice of
+    the given pitch inside the wall-cleared box, each jittered uniformly by up to
+    `jitter` per axis (pitch - diameter >= 2 jitter keeps the particles apart)."""
+    rng = SplitMix64(seed)
+    R = 0.5 * diameter
+    lo = -0.5 + R + clearance + jitter
+    axes = []
+    for a in range(dim):
+        hi = n[a] - 0.5 - R - clearance - jitter
+        m = int(math.floor((hi - lo) / pitch)) + 1
+        axes.append(lo + pitch * np.arange(m) + 0.5 * ((hi - lo) - pitch * (m - 1)))
+    grid = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, dim)
+    if count > len(grid):
+        raise ValueError("not enough lattice sites")
+    order = np.argsort(rng.uniform(len(grid)), kind="stable")[:count]
+    X = np.zeros((count, 3))
+    X[:, :dim] = grid[np.sort(order)] + rng.uniform(count * dim, -jitter, jitter).reshape(count, dim)
     return X
 
 
