@@ -314,21 +314,24 @@ def run_sweep(args):
 
 
 NP_SWEEP = {2: [1, 10, 100, 1000, 5000, 10000], 3: [1, 10, 100, 300, 600]}
+RES_SWEEP = {2: [12, 16, 24, 32, 40, 48], 3: [12, 16, 20, 24, 30]}
 
 
-def run_np_sweep(args):
-    """The particle-count series of Table 7 (Sec. 6.2.1): whole-step MLUPS and the time of
-    each kernel group per step as the number of particles grows in a fixed lattice
-    (2048^2 with D = 16, 150^3 with D = 12; FP32, MDF-3)."""
+def run_np_sweep(args, kind="np"):
+    """The particle-count series of Table 7 (Sec. 6.2.1; kind "np": 2048^2 with D = 16,
+    150^3 with D = 12) or the resolution series of Sec. 6.2.2 (kind "res": a 40 D square
+    with 400 disks, a 5 D cube with 27 spheres): whole-step MLUPS and the time of each
+    kernel group per step (FP32, MDF-3)."""
     import numpy as np
     import torch
 
     from paper_2002_08855_amd import binding, inputs
 
     rows = []
+    series = NP_SWEEP if kind == "np" else RES_SWEEP
     for dim in (2, 3):
-        for count in NP_SWEEP[dim]:
-            w = inputs.workload(f"np{dim}d_{count}")
+        for v in series[dim]:
+            w = inputs.workload(f"{kind}{dim}d_{v}")
             p, parts = w["params"], w["particles"]
             N = int(np.prod(p["n"]))
             sim = _sim(binding, p, parts)
@@ -342,14 +345,16 @@ def run_np_sweep(args):
             sim.set_timing(0)
             groups = {g: round(st["time_ms"][g] / 20, 5) for g in GROUPS if st["launches"][g]}
             np_, nmk = sim.counts()
-            rows.append({"dim": dim, "particles": np_, "points": nmk,
+            rows.append({"dim": dim, "n": list(p["n"][:dim]), "diameter": float(parts["diameter"][0]),
+                         "particles": np_, "points": nmk,
                          "mesh_ratio": round(nmk / N, 6), "mlups": r["value"],
                          "ms_per_step": r["ms_per_step"], "slip_rms": r["slip_rms"],
                          "kernel_ms_per_step": groups})
             print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
             del sim
             torch.cuda.empty_cache()
-    return {"sweep": "particle count (Table 7), FP32, MDF-3", "unit": "MLUPS", "rows": rows}
+    what = "particle count (Table 7)" if kind == "np" else "particle resolution (Sec. 6.2.2)"
+    return {"sweep": f"{what}, FP32, MDF-3", "unit": "MLUPS", "rows": rows}
 
 
 def cpu_baseline(w, args):
@@ -399,6 +404,9 @@ def main():
     ap.add_argument("--np-sweep", action="store_true",
                     help="instead of the headline line: MLUPS and kernel-group times against "
                          "the number of particles (Table 7)")
+    ap.add_argument("--res-sweep", action="store_true",
+                    help="instead of the headline line: the same against the particle "
+                         "resolution (Sec. 6.2.2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the IB-LBM step runs on one GPU; --gpus above 1 is not "
@@ -409,6 +417,9 @@ def main():
         return
     if args.np_sweep:
         print(json.dumps(run_np_sweep(args)), flush=True)
+        return
+    if args.res_sweep:
+        print(json.dumps(run_np_sweep(args, "res")), flush=True)
         return
     out = run(args)
     print(json.dumps(out), flush=True)

@@ -96,6 +96,9 @@ def workload(name: str) -> dict:
                         disks D=16 (Np <= 10^4), 150^3 FP32 with Np spheres D=12 (Np <= 600),
                         round(pi D) / round(pi D^2) points, ratio 1.5, MDF-3, on a thinned
                         square or cubic lattice (pitch 20 / 15, jitter 1).
+    res2d_<D> / res3d_<D>: the resolution series of Sec. 6.2.2: a 40 D square with 400
+                        disks (20 x 20 grid, pitch 2 D) / a 5 D cube with 27 spheres (pitch
+                        5 D / 3), diameter D, FP32, ratio 1.5, MDF-3.
     channel2d_<n> / channel3d_<n>: the particle-free flow of Sec. 6.1 on n^2 / n^3 nodes,
                         FP32, tau 0.6: inflow at the bottom (uniform 0.01 lattice units
                         per step) and outflow at the top (pressure 0) by non-equilibrium
@@ -121,6 +124,24 @@ def workload(name: str) -> dict:
                              pitch=15.0, clearance=2.5, jitter=1.0)
             D = 12.0
         parts = dict(center=X, diameter=np.full(count, D), density=np.full(count, 1.5),
+                     n_markers=0)
+        return dict(params=p, particles=parts, steps=200)
+    if name.startswith("res2d_") or name.startswith("res3d_"):
+        # the resolution series of Sec. 6.2.2: a 40 D square / 5 D cube with the particle
+        # diameter D in lattice units; the number of particles (400 / 27) and so the
+        # volume fraction (0.20 / 0.11) stay fixed
+        dim = 2 if name.startswith("res2d_") else 3
+        D = float(name.split("_")[1])
+        if dim == 2:
+            n = int(round(40 * D))
+            p = default_params(2, (n, n), tau=0.6, storage="f32", mdf_iters=3)
+            X = jittered_grid(seed=9, nx=20, ny=20, pitch=2 * D, origin=D, jitter=1.0)
+        else:
+            n = int(round(5 * D))
+            p = default_params(3, (n, n, n), tau=0.7, storage="f32", mdf_iters=3)
+            X = jittered_grid(seed=10, nx=3, ny=3, pitch=5 * D / 3, origin=5 * D / 6,
+                              jitter=1.0, nz=3)
+        parts = dict(center=X, diameter=np.full(len(X), D), density=np.full(len(X), 1.5),
                      n_markers=0)
         return dict(params=p, particles=parts, steps=200)
     if name.startswith("channel2d_") or name.startswith("channel3d_"):
