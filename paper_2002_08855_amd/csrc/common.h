@@ -134,7 +134,8 @@ struct iblbm_ctx {
   std::vector<double> hD, hX;  // host copies used for validation
   std::vector<int> hcount;
   double dmax = 0.0;
-  int box_cap = 0;     // nodes in the largest per-particle support box
+  int box_cap = 0;     // nodes in the largest work unit's support box
+  int full_side = 0;   // nodes a side of the largest particle's whole support box
   int lds_max = 65536; // LDS bytes a workgroup may use on this device
   bool ibm_lds = true; // per-particle LDS kernels for interpolation and spreading
   int band_pass = -1;   // band u* in its own pass (1) or in the first interpolation (0);
@@ -160,8 +161,18 @@ struct iblbm_ctx {
   int* pair_nup = nullptr;    // np
   int* pair_all = nullptr;    // np x PAIR_CAP all partners, ascending
   int* pair_nall = nullptr;   // np
-  uint16_t* tlist = nullptr;  // np x box_cap: touched box nodes of each particle, ascending
-  int* tcount = nullptr;      // np: entries of tlist per particle
+  // work units of the per-particle LDS kernels: one per particle, or runs of consecutive
+  // points of a particle too large for one workgroup, each with its own box
+  int npatch = 0;
+  bool patched = false;       // some particle has more than one unit
+  bool patch_ok = false;      // every unit fits one workgroup
+  int *pt_owner = nullptr, *pt_m0 = nullptr, *pt_mc = nullptr;  // npatch
+  double *pt_rlo = nullptr, *pt_rhi = nullptr;                  // npatch x 3 offset range
+  std::vector<int> hpt_mc;    // host copy of pt_mc
+  std::vector<int> hstart;    // host copy of mstart
+  std::vector<double> hmr;    // host copy of the point offsets (4 per point)
+  uint16_t* tlist = nullptr;  // npatch x box_cap: touched box nodes of each unit, ascending
+  int* tcount = nullptr;      // npatch: entries of tlist per unit
   // status and statistics
   int* dstatus = nullptr;     // [0] flags, [1] truncated (int64 at [2..3]), ...
   double* dstats = nullptr;   // [0] slip sum of squares
@@ -198,6 +209,7 @@ struct iblbm_ctx {
 };
 
 constexpr int CELL_CAP = 8;
+constexpr int LDS_THREADS = 1024;  // largest workgroup of the per-particle LDS kernels
 constexpr int PAIR_CAP = 24;
 constexpr int MAX_BOX_3D = 46;  // D <= 40 with a 4-point stencil
 

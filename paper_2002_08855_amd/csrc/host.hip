@@ -118,6 +118,114 @@ double compute_H(const iblbm_ctx* c) {
   return H;
 }
 
+// Work units of the per-particle LDS kernels.  A particle whose support box fits one
+// workgroup's LDS (at most floor(D) + 5 nodes a side, the box of +-R) and whose points
+// fit one workgroup is one unit.  A larger particle is split into runs of consecutive
+// points -- bands of the spiral on a sphere, arcs on a circle -- each with the box of
+// its own points' offset range; runs are halved until every box fits.  The units, the
+// largest box (box_cap) and patch_ok (false when even runs of 32 points do not fit, and
+// the point-wise kernels are used) are set on the context and copied to the device.
+void build_patches(iblbm_ctx* c) {
+  const int dim = c->dim;
+  const size_t cs = c->fp64 ? 8 : 4;
+  // LDS bytes per box node: interpolation (u, flag, list) and spreading (sums, list)
+  const double per_node = std::max<double>((double)(dim * cs + 3), (double)(dim * cs + 2));
+  long long nmax = (long long)((c->lds_max - 1024) / per_node);
+  nmax = std::min<long long>(nmax, 65536);
+  // box nodes per axis for an offset range of width w (see the device box)
+  auto side = [](double w) { return (long long)floor(w + 1e-6) + 5; };
+  std::vector<int> own, m0v, mcv;
+  std::vector<double> rlo, rhi;
+  long long cap = 1;
+  bool ok_all = true;
+  c->full_side = 0;
+  for (int p = 0; p < c->np; p++) {
+    const double D = c->hD[p], R = 0.5 * D;
+    const int m0 = c->hstart[p], mc = c->hcount[p];
+    c->full_side = std::max<int>(c->full_side, (int)side(D));
+    long long full = 1;
+    for (int a = 0; a < dim; a++) full *= side(D);
+    if (full <= nmax && mc <= LDS_THREADS) {
+      own.push_back(p);
+      m0v.push_back(m0);
+      mcv.push_back(mc);
+      for (int a = 0; a < 3; a++) {
+        rlo.push_back(a < dim ? -R : 0.0);
+        rhi.push_back(a < dim ? R : 0.0);
+      }
+      cap = std::max(cap, full);
+      continue;
+    }
+    bool done = false;
+    for (int P = std::min(mc, LDS_THREADS); P >= 32 && !done; P /= 2) {
+      std::vector<int> o2, m2, c2;
+      std::vector<double> l2, h2;
+      long long cap2 = 1;
+      bool ok = true;
+      for (int s = 0; s < mc && ok; s += P) {
+        const int e = std::min(mc, s + P);
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; a++) {
+          lo[a] = 1e300;
+          hi[a] = -1e300;
+          for (int k = s; k < e; k++) {
+            const double r = c->hmr[4 * (size_t)(m0 + k) + a];
+            lo[a] = std::min(lo[a], r);
+            hi[a] = std::max(hi[a], r);
+          }
+        }
+        long long n = 1;
+        for (int a = 0; a < dim; a++) n *= side(hi[a] - lo[a]);
+        if (n > nmax) {
+          ok = false;
+          break;
+        }
+        cap2 = std::max(cap2, n);
+        o2.push_back(p);
+        m2.push_back(m0 + s);
+        c2.push_back(e - s);
+        for (int a = 0; a < 3; a++) {
+          l2.push_back(lo[a]);
+          h2.push_back(hi[a]);
+        }
+      }
+      if (!ok) continue;
+      own.insert(own.end(), o2.begin(), o2.end());
+      m0v.insert(m0v.end(), m2.begin(), m2.end());
+      mcv.insert(mcv.end(), c2.begin(), c2.end());
+      rlo.insert(rlo.end(), l2.begin(), l2.end());
+      rhi.insert(rhi.end(), h2.begin(), h2.end());
+      cap = std::max(cap, cap2);
+      done = true;
+    }
+    if (!done) ok_all = false;
+  }
+  int* ip[] = {c->pt_owner, c->pt_m0, c->pt_mc};
+  for (int* q : ip)
+    if (q) dfree(c, q);
+  if (c->pt_rlo) dfree(c, c->pt_rlo);
+  if (c->pt_rhi) dfree(c, c->pt_rhi);
+  c->pt_owner = c->pt_m0 = c->pt_mc = nullptr;
+  c->pt_rlo = c->pt_rhi = nullptr;
+  c->patch_ok = ok_all;
+  c->npatch = ok_all ? (int)own.size() : c->np;
+  c->patched = ok_all && c->npatch > c->np;
+  c->box_cap = (int)std::min<long long>(cap, 1LL << 30);
+  c->hpt_mc = ok_all ? mcv : c->hcount;
+  if (!ok_all || c->npatch == 0) return;
+  c->pt_owner = dzeros<int>(c, own.size());
+  c->pt_m0 = dzeros<int>(c, own.size());
+  c->pt_mc = dzeros<int>(c, own.size());
+  c->pt_rlo = dzeros<double>(c, rlo.size());
+  c->pt_rhi = dzeros<double>(c, rhi.size());
+  HIPCHK(hipMemcpyAsync(c->pt_owner, own.data(), own.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pt_m0, m0v.data(), m0v.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pt_mc, mcv.data(), mcv.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pt_rlo, rlo.data(), rlo.size() * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pt_rhi, rhi.data(), rhi.size() * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
 // Lagrangian points: equal angles on a circle (2-D); golden-angle spiral on a sphere
 // (3-D), z_k = 1 - (2k+1)/N_L, azimuth k pi (3 - sqrt 5).
 void marker_offsets(int dim, double R, int nl, std::vector<double>& r) {
@@ -570,14 +678,8 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     c->hX = allX;
     c->hD = allD;
     c->hcount.insert(c->hcount.end(), mcount.begin(), mcount.end());
-    // per-particle support box of the largest particle (at most floor(D + 2e-9) + 5
-    // nodes per axis, the 1e-9 widening of the box radius included)
-    {
-      double dmax = 0;
-      for (double d : allD) dmax = std::max(dmax, d);
-      int B = (int)floor(dmax + 2e-9) + 5;
-      c->box_cap = dim == 2 ? B * B : B * B * B;
-    }
+    c->hstart.insert(c->hstart.end(), mstart.begin(), mstart.end());
+    c->hmr.insert(c->hmr.end(), mr.begin(), mr.end());
     // cell grid (Eqs. 49-50) and pair buffers
     double H = compute_H(c);
     long long ncell = 1;
@@ -602,10 +704,12 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     if (c->pair_nup) dfree(c, c->pair_nup);
     if (c->pair_all) dfree(c, c->pair_all);
     if (c->pair_nall) dfree(c, c->pair_nall);
+    // work units of the per-particle LDS kernels and their touched-node lists
+    build_patches(c);
     if (c->tlist) dfree(c, c->tlist);
     if (c->tcount) dfree(c, c->tcount);
-    c->tlist = dzeros<uint16_t>(c, (size_t)np * (c->box_cap <= 65536 ? c->box_cap : 1));
-    c->tcount = dzeros<int>(c, (size_t)np);
+    c->tlist = dzeros<uint16_t>(c, (size_t)c->npatch * (c->box_cap <= 65536 ? c->box_cap : 1));
+    c->tcount = dzeros<int>(c, (size_t)c->npatch);
     c->cell_of = dzeros<int>(c, 3 * (size_t)np);
     c->pair_up = dzeros<int>(c, (size_t)np * PAIR_CAP);
     c->pair_nup = dzeros<int>(c, (size_t)np);

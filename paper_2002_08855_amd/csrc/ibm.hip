@@ -328,18 +328,20 @@ struct PBox {
   }
 };
 
-// The box of nodes that the supports of a particle's points can reach.  R is widened by
-// 1e-9 so that a point whose offset from the centre rounds to slightly more than R
-// still has its support inside; the box side is at most floor(D + 2e-9) + 5 nodes.
+// The box of nodes that the supports of points at offsets in [rlo, rhi] from Xc can
+// reach.  The range is widened by 1e-9 so that a point whose offset rounds slightly
+// outside still has its support inside; the box side is at most
+// floor(rhi - rlo + 2e-9) + 5 nodes.
 template <int DIM>
-__device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, int kind) {
+__device__ __forceinline__ PBox<DIM> range_box(const double* Xc, const double* rlo,
+                                               const double* rhi, int kind) {
   PBox<DIM> b;
   b.n = 1;
-  R += 1e-9;
   for (int d = 0; d < 3; d++) {
     if (d < DIM) {
-      int lo = kind == 0 ? int(floor(Xc[d] - R)) - 1 : int(floor(Xc[d] - R + 0.5)) - 1;
-      int hi = kind == 0 ? int(floor(Xc[d] + R)) + 2 : int(floor(Xc[d] + R + 0.5)) + 1;
+      const double l = Xc[d] + (rlo[d] - 1e-9), h = Xc[d] + (rhi[d] + 1e-9);
+      int lo = kind == 0 ? int(floor(l)) - 1 : int(floor(l + 0.5)) - 1;
+      int hi = kind == 0 ? int(floor(h)) + 2 : int(floor(h + 0.5)) + 1;
       b.lo[d] = lo;
       b.B[d] = hi - lo + 1;
     } else {
@@ -374,15 +376,47 @@ struct LdsArgs {
   int nwx;         // words per row
   const int* cond; // run only when *cond != 0 (if set)
   int mcap;        // points of the largest particle
-  uint16_t* tlist; // touched box nodes per particle (cap entries each), ascending
+  uint16_t* tlist; // touched box nodes per work unit (cap entries each), ascending
   int* tcount;
+  // work units: with patched == 0 the unit is the particle (box of +-D/2); otherwise
+  // unit q is the run of pt_mc[q] points from pt_m0[q] of particle pt_owner[q], with the
+  // box of the offset range [pt_rlo, pt_rhi]
+  int patched;
+  const int *pt_owner, *pt_m0, *pt_mc;
+  const double *pt_rlo, *pt_rhi;
   // PDF access for the first pass
   Geo<C> geo;
   SlotPtrs slot;
   C inv_s;
 };
 
-constexpr int LDS_THREADS = 1024;
+// the box of a whole particle: offsets within +-R of its centre
+template <int DIM>
+__device__ __forceinline__ PBox<DIM> particle_box(const double* Xc, double R, int kind) {
+  const double rlo[3] = {-R, -R, -R}, rhi[3] = {R, R, R};
+  return range_box<DIM>(Xc, rlo, rhi, kind);
+}
+
+// The work unit of block q: its particle, first point, point count and box.
+template <int DIM, class C>
+__device__ __forceinline__ void unit_of(const LdsArgs<C>& a, int q, int& p, int& m0, int& mc,
+                                        PBox<DIM>& b) {
+  if (a.patched) {
+    p = a.pt_owner[q];
+    m0 = a.pt_m0[q];
+    mc = a.pt_mc[q];
+  } else {
+    p = q;
+    m0 = a.mstart[p];
+    mc = a.mcount[p];
+  }
+  const double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
+  if (a.patched)
+    b = range_box<DIM>(Xc, a.pt_rlo + 3 * (size_t)q, a.pt_rhi + 3 * (size_t)q, a.g.kind);
+  else
+    b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
+}
+
 
 // List entries a lane loads before it uses any of them, so that their global-memory
 // latencies overlap.
@@ -618,13 +652,13 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
   const bool stop = halted(a.P.status);
   int* wcnt = reinterpret_cast<int*>(smem_d);
   uint8_t* flag = reinterpret_cast<uint8_t*>(wcnt + 20);
-  int p = blockIdx.x;
-  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
-  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  if (stop || b.n > a.cap) return;  // the host sizes cap for the largest particle
+  const int q = blockIdx.x;
+  int p, m0, mc;
+  PBox<DIM> b;
+  unit_of<DIM>(a, q, p, m0, mc, b);
+  if (stop || b.n > a.cap) return;  // the host sizes cap for the largest unit
   for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
   __syncthreads();
-  int m0 = a.mstart[p], mc = a.mcount[p];
   for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
     double X[3], Ub[3];
     marker_pos_vel(a.P, k, X, Ub, DIM);
@@ -633,9 +667,9 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
     visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
   }
   __syncthreads();
-  uint16_t* tl = a.tlist + (size_t)p * a.cap;
+  uint16_t* tl = a.tlist + (size_t)q * a.cap;
   const int ntouch = list_flags(flag, b.n, tl, wcnt);
-  if (threadIdx.x == 0) a.tcount[p] = ntouch;
+  if (threadIdx.x == 0) a.tcount[q] = ntouch;
   for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
     const int t = tl[j];
     int x, y, z;
@@ -670,11 +704,11 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   uint8_t* flag = reinterpret_cast<uint8_t*>(base + Ly.flag);
   uint16_t* list = reinterpret_cast<uint16_t*>(base + Ly.list);
   int* wcnt = reinterpret_cast<int*>(base + Ly.wcnt);
-  int p = blockIdx.x;
-  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
-  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  int m0 = a.mstart[p], mc = a.mcount[p];
-  // the host sizes cap and the block for the largest particle
+  const int q = blockIdx.x;
+  int p, m0, mc;
+  PBox<DIM> b;
+  unit_of<DIM>(a, q, p, m0, mc, b);
+  // the host sizes cap and the block for the largest unit
   if (stop || b.n > a.cap || mc > (int)blockDim.x) return;
   // this lane's point, loaded and weighted before the box is staged so that the
   // latencies overlap; with an accumulating pass also its force so far
@@ -691,7 +725,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
     }
     point_weights<DIM, C>(a.g.kind, X, pw);
   }
-  uint16_t* tl = a.tlist + (size_t)p * a.cap;
+  uint16_t* tl = a.tlist + (size_t)q * a.cap;
   int ntouch;
   const uint16_t* nodes;
   if (FIRST) {
@@ -701,11 +735,11 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
     if (has) visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
     __syncthreads();
     ntouch = list_flags(flag, b.n, list, wcnt);
-    if (threadIdx.x == 0) a.tcount[p] = ntouch;
+    if (threadIdx.x == 0) a.tcount[q] = ntouch;
     for (int j = threadIdx.x; j < ntouch; j += blockDim.x) tl[j] = list[j];
     nodes = list;
   } else {
-    ntouch = a.tcount[p];
+    ntouch = a.tcount[q];
     nodes = tl;
   }
   T* slot[L::Q - 1];
@@ -835,11 +869,11 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   U* acc = reinterpret_cast<U*>(smem_d);
   double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_d) +
                                           spread_acc_bytes(DIM, sizeof(C), a.cap));
-  int p = blockIdx.x;
-  double Xc[3] = {a.P.X[3 * p], a.P.X[3 * p + 1], DIM == 3 ? a.P.X[3 * p + 2] : 0.0};
-  PBox<DIM> b = particle_box<DIM>(Xc, 0.5 * a.D[p], a.g.kind);
-  int m0 = a.mstart[p], mc = a.mcount[p];
-  // the host sizes the box and the block for the largest particle
+  const int q = blockIdx.x;
+  int p, m0, mc;
+  PBox<DIM> b;
+  unit_of<DIM>(a, q, p, m0, mc, b);
+  // the host sizes the box and the block for the largest unit
   if (stop || b.n > a.cap || mc > (int)blockDim.x) return;
   const int kind = a.g.kind, width = a.g.width;
   // this lane's point: 1-D weights, first support node, force times drs*ds (Eq. 13)
@@ -875,8 +909,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   // the touched nodes of the step (listed by the marking kernel or the first pass),
   // copied into LDS after the point loads above are issued, so that the latencies overlap
   uint16_t* tl = reinterpret_cast<uint16_t*>(red + 16);
-  const uint16_t* gl = a.tlist + (size_t)p * a.cap;
-  const int ntouch = a.tcount[p];
+  const uint16_t* gl = a.tlist + (size_t)q * a.cap;
+  const int ntouch = a.tcount[q];
   for (int j0 = threadIdx.x; j0 < ntouch; j0 += LIST_BATCH * blockDim.x) {
     int t[LIST_BATCH];
 #pragma unroll
@@ -1036,15 +1070,11 @@ InterpArgs<C> make_interp_args(iblbm_ctx* c, int first, int mode) {
 }
 
 // points of the largest particle
+// points of the largest work unit
 int max_points(const iblbm_ctx* c) {
   int mx = 1;
-  for (int m : c->hcount) mx = m > mx ? m : mx;
+  for (int m : c->hpt_mc) mx = m > mx ? m : mx;
   return mx;
-}
-
-// side of the largest particle's box
-int box_side(const iblbm_ctx* c) {
-  return c->box_cap > 0 ? (int)llround(pow((double)c->box_cap, 1.0 / c->dim)) : 0;
 }
 
 template <class T>
@@ -1075,6 +1105,12 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.mcap = max_points(c);
   a.tlist = c->tlist;
   a.tcount = c->tcount;
+  a.patched = c->patched ? 1 : 0;
+  a.pt_owner = c->pt_owner;
+  a.pt_m0 = c->pt_m0;
+  a.pt_mc = c->pt_mc;
+  a.pt_rlo = c->pt_rlo;
+  a.pt_rhi = c->pt_rhi;
   a.geo = make_geo<C>(c);
   a.slot = make_slots(c);
   a.inv_s = inv_scale<T>(c);
@@ -1144,7 +1180,7 @@ struct RunInterp {
     if (!FIRST) bytes = ((size_t)DIM * c->box_cap * sizeof(C) + 7) & ~(size_t)7;
     auto k = k_interp_lds<DIM, T, PAR, FIRST>;
     raise_lds_limit((const void*)k, c->lds_max);
-    hipLaunchKernelGGL(k, dim3(c->np), dim3(interp_threads(c)), bytes, c->stream, a);
+    hipLaunchKernelGGL(k, dim3(c->npatch), dim3(interp_threads(c)), bytes, c->stream, a);
   }
 };
 
@@ -1155,7 +1191,7 @@ struct RunMarkLds {
     using C = typename Store<T>::C;
     auto a = make_lds_args<T>(c, 0, 0);
     size_t bytes = 20 * sizeof(int) + (((size_t)c->box_cap + 3) & ~(size_t)3);
-    hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
+    hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->npatch), dim3(lds_threads(c)), bytes, c->stream, a);
   }
 };
 
@@ -1177,7 +1213,7 @@ struct RunSpread {
     auto a = make_lds_args<T>(c, 0, 0);
     auto k = k_spread_lds<DIM, C>;
     raise_lds_limit((const void*)k, c->lds_max);
-    hipLaunchKernelGGL(k, dim3(c->np), dim3(lds_threads(c)), bytes, c->stream, a);
+    hipLaunchKernelGGL(k, dim3(c->npatch), dim3(lds_threads(c)), bytes, c->stream, a);
     *done = true;
   }
 };
@@ -1224,7 +1260,8 @@ void run_point_spread(iblbm_ctx* c) {
 
 bool ibm_uses_lds(const iblbm_ctx* c) {
   size_t cs = c->fp64 ? 8 : 4;
-  return c->ibm_lds && c->box_cap > 0 && c->box_cap <= 65536 && max_points(c) <= LDS_THREADS &&
+  return c->ibm_lds && c->patch_ok && c->box_cap > 0 && c->box_cap <= 65536 &&
+         max_points(c) <= LDS_THREADS &&
          lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
          lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
@@ -1265,7 +1302,7 @@ void ibm_band(iblbm_ctx* c) {
   a.nsegx = (int)c->nsegx;
   {
     // box side <= floor(D) + 7 nodes, so <= side/16 + 2 segments per row
-    int side = (int)llround(pow((double)c->box_cap, 1.0 / c->dim)) + 3;
+    int side = c->full_side + 3;
     long long nbits = (long long)(side / SEG + 2) * (c->dim == 3 ? (long long)side * side : side);
     a.words = (int)std::min<long long>((nbits + 31) / 32, 8192);
   }

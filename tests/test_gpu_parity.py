@@ -261,17 +261,42 @@ def test_particles_added_in_two_batches():
     assert np.abs(pg["Omega"] - po["Omega"]).max() < 1e-11 * scale
 
 
-def test_large_sphere_takes_the_point_wise_kernels():
-    """A sphere whose support box exceeds the per-particle LDS limit (D = 36: 41^3 box
-    nodes) is handled by the point-wise kernels with no option set; FP64 parity."""
+@pytest.mark.parametrize("lds", [1, 0])
+def test_large_sphere(lds):
+    """A sphere whose support box exceeds one workgroup's LDS (D = 28: 33^3 box nodes of
+    FP64 sums, 2463 points) is split into runs of consecutive points, bands of the
+    spiral with boxes of their own (or handled by the point-wise kernels); FP64
+    parity."""
     p = inputs.default_params(3, (52, 50, 48), tau=0.8, storage="f64", mdf_iters=2)
     g, o = _pair(p)
+    g.set_ibm_lds(lds)
     for s in (g, o):
-        s.add_particles([[26.2, 24.7, 23.9]], [36.0], [1.5], n_markers=0)
+        s.add_particles([[26.2, 24.7, 23.9]], [28.0], [1.5], n_markers=0)
     g.step(8)
     o.step(8)
-    _compare_fields(g, o, 1e-12, "large sphere")
+    _compare_fields(g, o, 1e-12, f"large sphere lds={lds}")
     assert rel_l2(g.particles()["U"], o.particles()["U"]) < 1e-11
+
+
+@pytest.mark.parametrize("band", [None, 1])
+def test_disks_with_more_points_than_a_workgroup(band):
+    """Disks with 2000 points (more than one workgroup's 1024 lanes) next to a small one:
+    the large disks are split into runs of points, the small one stays whole; FP64
+    parity over both step parities."""
+    p = inputs.default_params(2, (120, 100), tau=0.8, storage="f64", mdf_iters=3)
+    g, o = _pair(p)
+    if band is not None:
+        g.set_band_pass(band)
+    for s in (g, o):
+        s.add_particles([[40.3, 50.2, 0.0], [88.6, 48.9, 0.0]], [40.0, 30.0], [1.5, 1.5],
+                        n_markers=2000)
+        s.add_particles([[95.0, 12.0, 0.0]], [10.0], [1.5], n_markers=32)
+    g.step(40)
+    o.step(40)
+    _compare_fields(g, o, 1e-12, f"many-point disks band={band}")
+    pg, po = g.particles(), o.particles()
+    for k in ("X", "U", "F_h"):
+        assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))
 
 
 @pytest.mark.parametrize("case", ["overlap", "outside", "wall_gap"])
