@@ -118,13 +118,16 @@ double compute_H(const iblbm_ctx* c) {
   return H;
 }
 
-// Work units of the per-particle LDS kernels.  A particle whose support box fits one
-// workgroup's LDS (at most floor(D) + 5 nodes a side, the box of +-R) and whose points
-// fit one workgroup is one unit.  A larger particle is split into runs of consecutive
-// points -- bands of the spiral on a sphere, arcs on a circle -- each with the box of
-// its own points' offset range; runs are halved until every box fits.  The units, the
-// largest box (box_cap) and patch_ok (false when even runs of 32 points do not fit, and
-// the point-wise kernels are used) are set on the context and copied to the device.
+// Work units of the per-particle LDS kernels.  A particle whose support box fits in
+// half of a compute unit's LDS (at most floor(D) + 5 nodes a side, the box of +-R) and
+// whose points fit one workgroup is one unit.  Any other particle is split into runs of
+// consecutive points -- bands of the spiral on a sphere, arcs on a circle -- each with
+// the box of its own points' offset range: two runs if the whole box fits one workgroup
+// but leaves no room for a second (a 16-wide FP32 sphere: about 5% faster steps, while
+// three or more runs cost more in atomics at the seams than they gain), else runs
+// halved until every box fits.  The units, the largest box (box_cap) and patch_ok
+// (false when even runs of 32 points do not fit, and the point-wise kernels are used)
+// are set on the context and copied to the device.
 void build_patches(iblbm_ctx* c) {
   const int dim = c->dim;
   const size_t cs = c->fp64 ? 8 : 4;
@@ -145,7 +148,7 @@ void build_patches(iblbm_ctx* c) {
     c->full_side = std::max<int>(c->full_side, (int)side(D));
     long long full = 1;
     for (int a = 0; a < dim; a++) full *= side(D);
-    if (full <= nmax && mc <= LDS_THREADS) {
+    if (2 * full <= nmax && mc <= LDS_THREADS) {
       own.push_back(p);
       m0v.push_back(m0);
       mcv.push_back(mc);
@@ -157,7 +160,8 @@ void build_patches(iblbm_ctx* c) {
       continue;
     }
     bool done = false;
-    for (int P = std::min(mc, LDS_THREADS); P >= 32 && !done; P /= 2) {
+    const int P0 = full <= nmax && mc >= 64 ? (mc + 1) / 2 : mc;
+    for (int P = std::min(P0, LDS_THREADS); P >= 32 && !done; P /= 2) {
       std::vector<int> o2, m2, c2;
       std::vector<double> l2, h2;
       long long cap2 = 1;

@@ -16,8 +16,8 @@ Two steps, both run by hand:
 
    FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch; each is scaled by the
    ratio of the copy's known bytes to what the same counter read for the copy.  The
-   result records the hash of the kernel's source file so that a reader can tell when
-   it no longer describes the built kernel.
+   result records a hash of the kernel's source and of the host code that launches it,
+   so that a reader can tell when it no longer describes the built kernel.
 """
 from __future__ import annotations
 
@@ -38,9 +38,10 @@ SOURCE_OF = {"k_collide_stream": "lbm.hip", "k_interior": "lbm.hip", "k_interp_l
 
 
 def source_sha(kernel):
-    """hash of the kernel's source file and the headers every kernel includes"""
+    """hash of the kernel's source file, the headers every kernel includes and the host
+    code that sets the launch shapes and work units"""
     h = hashlib.sha256()
-    for f in (SOURCE_OF[kernel], "common.h", "pdf_access.h"):
+    for f in (SOURCE_OF[kernel], "common.h", "pdf_access.h", "host.hip"):
         h.update(open(os.path.join(ROOT, "paper_2002_08855_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
