@@ -193,7 +193,9 @@ def test_cavity3d_particles(lds, storage, tol, band, btdf):
     """A 3-D cavity with spheres touching the walls' stencil margins, with MDF-3 and the
     4-point kernel or the single-pass thickened shell (3-point kernel, drs = 1.9): fields
     within the storage tolerance; per-particle kernels with the band u* in its own pass
-    (the 3-D default) or inside the first interpolation, and the point-wise kernels."""
+    (the 3-D default) or inside the first interpolation, and the point-wise kernels.  In
+    FP64 a sphere's 15^3 box of sums takes more than half of the LDS, so each sphere runs
+    as two bands of 157 points; in FP32 it stays one unit."""
     n = (48, 44, 40)
     p = inputs.default_params(3, n, tau=0.7, storage=storage, mdf_iters=3)
     if btdf:
