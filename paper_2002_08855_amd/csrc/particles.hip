@@ -265,40 +265,62 @@ __global__ __launch_bounds__(256) void k_loads_newton(LoadArgs<C> a) {
     for (int k = 0; k < 6; k++) red[k][threadIdx.x >> 6] = acc[k];
   __syncthreads();
   if (threadIdx.x != 0) return;
+  const PartArgs& q = a.pa;
+  // every operand of the update is loaded before the first store, so that the loads share
+  // one memory latency instead of each waiting behind the stores of earlier components
+  double M = 0.0, V = 0.0, I = 0.0;
+  double U0[3], Om0[3], Pin[3], Ppr[3], Hpr[3], Lin[3], Lpr[3], Gpr[3], Fc[3], X0[3];
+  int cl[3] = {0, 0, 0};
+  if (a.update) {
+    M = a.M[p];
+    V = a.V[p];
+    I = a.I[p];
+    for (int d = 0; d < 3; d++) {
+      U0[d] = q.U[3 * p + d];
+      Om0[d] = q.Om[3 * p + d];
+      Pin[d] = a.Pin[3 * p + d];
+      Ppr[d] = a.Pprev[3 * p + d];
+      Hpr[d] = a.Hprev[3 * p + d];
+      Lin[d] = a.Lin[3 * p + d];
+      Lpr[d] = a.Lprev[3 * p + d];
+      Gpr[d] = a.Gprev[3 * p + d];
+      Fc[d] = q.Fc[3 * p + d];
+      X0[d] = a.X[3 * p + d];
+      cl[d] = q.cell_of[3 * p + d];
+    }
+  }
   for (int v = 1; v < (int)(blockDim.x >> 6); v++)
     for (int k = 0; k < 6; k++) red[k][0] += red[k][v];
-  const PartArgs& q = a.pa;
   for (int d = 0; d < 3; d++) {
     q.Fh[3 * p + d] = red[d][0];
     q.Th[3 * p + d] = red[3 + d][0];
   }
   if (!a.update) return;
-  double meff = a.M[p] - q.rho0 * a.V[p];
+  double meff = M - q.rho0 * V;
   bool bad = false;
   for (int d = 0; d < q.dim; d++) {
-    double U0 = q.U[3 * p + d];
-    double H = red[d][0] + (a.Pin[3 * p + d] - a.Pprev[3 * p + d]);
-    double Havg = 0.5 * (H + a.Hprev[3 * p + d]);
-    double U1 = U0 + (Havg + q.Fc[3 * p + d] + meff * q.g[d]) / a.M[p];
+    double H = red[d][0] + (Pin[d] - Ppr[d]);
+    double Havg = 0.5 * (H + Hpr[d]);
+    double U1 = U0[d] + (Havg + Fc[d] + meff * q.g[d]) / M;
     a.Hprev[3 * p + d] = H;
     q.U[3 * p + d] = U1;
-    a.X[3 * p + d] = a.X[3 * p + d] + 0.5 * (U0 + U1);
+    a.X[3 * p + d] = X0[d] + 0.5 * (U0[d] + U1);
     bad |= !(U1 == U1) || fabs(U1) > 1.0;
   }
   for (int d = (q.dim == 2 ? 2 : 0); d < 3; d++) {
-    double G = red[3 + d][0] + (a.Lin[3 * p + d] - a.Lprev[3 * p + d]);
-    double Gavg = 0.5 * (G + a.Gprev[3 * p + d]);
+    double G = red[3 + d][0] + (Lin[d] - Lpr[d]);
+    double Gavg = 0.5 * (G + Gpr[d]);
     a.Gprev[3 * p + d] = G;
-    q.Om[3 * p + d] = q.Om[3 * p + d] + Gavg / a.I[p];
-    bad |= !(q.Om[3 * p + d] == q.Om[3 * p + d]);
+    const double Om1 = Om0[d] + Gavg / I;
+    q.Om[3 * p + d] = Om1;
+    bad |= !(Om1 == Om1);
   }
   for (int d = 0; d < 3; d++) {
-    a.Pprev[3 * p + d] = a.Pin[3 * p + d];
-    a.Lprev[3 * p + d] = a.Lin[3 * p + d];
+    a.Pprev[3 * p + d] = Pin[d];
+    a.Lprev[3 * p + d] = Lin[d];
   }
   // empty this particle's cell for the next cell-list build
-  int c0 = q.cell_of[3 * p], c1 = q.cell_of[3 * p + 1], c2 = q.cell_of[3 * p + 2];
-  q.cell_count[c0 + (long long)q.nc[0] * (c1 + (long long)q.nc[1] * c2)] = 0;
+  q.cell_count[cl[0] + (long long)q.nc[0] * (cl[1] + (long long)q.nc[1] * cl[2])] = 0;
   if (bad) atomicOr(q.status, ST_NAN);
 }
 
