@@ -89,13 +89,14 @@ __device__ double pair_mag(double d, double D, double zeta, double c, double eps
 constexpr int MAXP = 32;
 
 // One wavefront per particle: lanes scan the 5^d cells around it, candidates are
-// compacted with ballots into LDS, then one lane sorts the partners, sums the pair
-// forces in ascending partner order (pairs first, then the wall images in face order)
-// and writes the partners j > i for the pair list.
+// compacted with ballots into LDS and ranked into ascending order; each lane computes one
+// partner's pair force and writes the pair lists, and one lane sums the forces in
+// ascending partner order (pairs first, then the wall images in face order).
 __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
   // tested after the cell loads are issued, so that the latencies overlap
   const bool stop = halted(a.status);
-  __shared__ int cand[4][MAXP];
+  __shared__ int cand[4][MAXP], srt[4][MAXP];
+  __shared__ double cf[4][MAXP][3];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int i = blockIdx.x * 4 + wv;
   bool act = i < a.np;
@@ -156,29 +157,20 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
     }
   }
   __syncthreads();
-  if (!act || lane != 0) {
-    if (over) atomicOr(a.status, ST_PAIR_OVERFLOW);
-    return;
+  // the candidates are distinct: each lane ranks its own among them, which sorts them
+  const int cnt = act ? min(ncand, MAXP) : 0;
+  if (lane < cnt) {
+    const int j = cand[wv][lane];
+    int r = 0;
+    for (int k = 0; k < cnt; k++) r += cand[wv][k] < j ? 1 : 0;
+    srt[wv][r] = j;
   }
-  int cnt = min(ncand, MAXP);
-  int nb[MAXP];
-  for (int k = 0; k < cnt; k++) {
-    int j = cand[wv][k];
-    int q = k;
-    while (q > 0 && nb[q - 1] > j) {
-      nb[q] = nb[q - 1];
-      q--;
-    }
-    nb[q] = j;
-  }
-  const double* Xi = a.X + 3 * i;
-  double F[3] = {0.0, 0.0, 0.0};
-  int nup = 0;
-  for (int k = 0; k < cnt && k < PAIR_CAP; k++) a.pair_all[i * PAIR_CAP + k] = nb[k];
-  a.pair_nall[i] = min(cnt, PAIR_CAP);
-  for (int k = 0; k < cnt; k++) {
-    int j = nb[k];
-    int pa = i < j ? i : j, pb = i < j ? j : i;
+  __syncthreads();
+  // lane k: the k-th partner in ascending order and its Eq. 16 force on particle i, with
+  // the sign that the ordered sum below applies
+  const int jl = lane < cnt ? srt[wv][lane] : -1;
+  if (lane < cnt) {
+    const int pa = i < jl ? i : jl, pb = i < jl ? jl : i;
     double dx[3] = {0.0, 0.0, 0.0}, d2 = 0.0;
     for (int d = 0; d < a.dim; d++) {
       dx[d] = a.X[3 * pa + d] - a.X[3 * pb + d];
@@ -187,18 +179,31 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
     double dist = sqrt(d2);
     double mag = pair_mag(dist, 0.5 * (a.D[pa] + a.D[pb]), a.zeta, 0.5 * (a.cb[pa] + a.cb[pb]),
                           a.eps_pp, a.E_pp);
-    for (int d = 0; d < a.dim; d++) {
-      double Fa = mag * (dx[d] / dist);
-      F[d] = i == pa ? F[d] + Fa : F[d] - Fa;
+    for (int d = 0; d < 3; d++) {
+      double Fa = d < a.dim ? mag * (dx[d] / dist) : 0.0;
+      cf[wv][lane][d] = i == pa ? Fa : -Fa;
     }
-    if (j > i) {
-      if (nup < PAIR_CAP)
-        a.pair_up[i * PAIR_CAP + nup] = j;
-      else
-        over = true;
-      nup++;
-    }
+    if (lane < PAIR_CAP) a.pair_all[i * PAIR_CAP + lane] = jl;
   }
+  // the partners j > i are a suffix of the ascending list
+  const int nlow = __popcll(__ballot(lane < cnt && jl < i));
+  if (lane < cnt && jl > i) {
+    if (lane - nlow < PAIR_CAP)
+      a.pair_up[i * PAIR_CAP + (lane - nlow)] = jl;
+    else
+      over = true;
+  }
+  __syncthreads();
+  if (!act || lane != 0) {
+    if (over) atomicOr(a.status, ST_PAIR_OVERFLOW);
+    return;
+  }
+  const double* Xi = a.X + 3 * i;
+  // pair forces summed in ascending partner order (x - y and x + (-y) round alike)
+  double F[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < cnt; k++)
+    for (int d = 0; d < a.dim; d++) F[d] = F[d] + cf[wv][k][d];
+  const int nup = cnt - nlow;
   // walls: Eq. 16 against the mirror image in each wall plane (at -1/2 and n - 1/2)
   for (int d = 0; d < a.dim; d++) {
     if (a.periodic[d]) continue;
