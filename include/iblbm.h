@@ -182,6 +182,20 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
                                     steps whose index is a multiple of the value carry
                                     events, so that the events' own cost stays small */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
+/* Work units of the per-particle interpolation and spreading kernels for one particle:
+ * host-side planning only, no device call; iblbm_add_particles applies the same plan to
+ * each particle (Sec. 4: every surface point's delta-function support, Eqs. 47-48, must
+ * lie in the LDS box of its unit).  dim: 2 or 3; storage: an iblbm_storage (F64 sums take
+ * 8 bytes a component, the others 4); lds_bytes: LDS of one workgroup (0: 163840, the
+ * 160 KB of a gfx950 compute unit); diameter in (0, 4096]; n_points: surface points (0: the
+ * default count of iblbm_add_particles).  *n_units receives the number of units, 0 when
+ * the particle takes the point-wise kernels.  For the first min(*n_units, cap) units,
+ * first[u] and count[u] receive the unit's run of consecutive points and box_nodes[u] an
+ * upper bound on the nodes of its LDS box (NULL arrays are skipped).  IBLBM_E_ARG for
+ * arguments out of range, IBLBM_E_NOMEM if host memory runs out. */
+iblbm_status iblbm_plan_units(int32_t dim, int32_t storage, int32_t lds_bytes, double diameter,
+                              int32_t n_points, int32_t cap, int32_t* n_units, int32_t* first,
+                              int32_t* count, int64_t* box_nodes);
 /* on != 0: run steps through HIP graphs.  A step's kernel launches are captured the
  * first time its (PDF parity, band-bitmap buffer) pair occurs and replayed afterwards;
  * changes of state (particles, PDFs, options, MLP) drop the graphs.  Timed steps and

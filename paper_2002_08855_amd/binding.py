@@ -93,6 +93,8 @@ def lib():
             "iblbm_reset_stats": (C.c_int, [vp]),
             "iblbm_set_graph": (C.c_int, [vp, C.c_int32]),
             "iblbm_set_option": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "iblbm_plan_units": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                           C.c_int32, _i32, _i32, _i32, _P(C.c_int64)]),
             "iblbm_set_mlp": (C.c_int, [vp, _f, _f]),
             "iblbm_capture_samples": (C.c_int, [vp, _f, _f]),
             "iblbm_nn_train": (C.c_int, [_f, _f, C.c_int64, _f, _P(TrainOpts), _f]),
@@ -330,6 +332,23 @@ class Sim:
 def _raise(st, what):
     if st != 0:
         raise IblbmError(st, what)
+
+
+def plan_units(dim, storage, diameter, n_points=0, lds_bytes=0):
+    """Work units of the per-particle kernels for one particle (host-side planning):
+    a list of (first point, point count, box-node bound); empty when the particle takes
+    the point-wise kernels."""
+    st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    n = C.c_int32()
+    _raise(lib().iblbm_plan_units(dim, st, lds_bytes, float(diameter), n_points, 0, C.byref(n),
+                                  None, None, None), "iblbm_plan_units")
+    first = np.zeros(n.value, np.int32)
+    count = np.zeros(n.value, np.int32)
+    nodes = np.zeros(n.value, np.int64)
+    _raise(lib().iblbm_plan_units(dim, st, lds_bytes, float(diameter), n_points, n.value,
+                                  C.byref(n), _ip(first), _ip(count),
+                                  nodes.ctypes.data_as(_P(C.c_int64))), "iblbm_plan_units")
+    return list(zip(first.tolist(), count.tolist(), nodes.tolist()))
 
 
 def nn_forward(params, x):

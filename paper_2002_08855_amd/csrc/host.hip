@@ -125,84 +125,94 @@ double compute_H(const iblbm_ctx* c) {
 // the box of its own points' offset range: two runs if the whole box fits one workgroup
 // but leaves no room for a second (a 16-wide FP32 sphere: about 5% faster steps, while
 // three or more runs cost more in atomics at the seams than they gain), else runs
-// halved until every box fits.  The units, the largest box (box_cap) and patch_ok
-// (false when even runs of 32 points do not fit, and the point-wise kernels are used)
-// are set on the context and copied to the device.
+// halved until every box fits.  A particle for which even runs of 32 points do not fit
+// has no plan (the point-wise kernels are used).
+struct UnitPlan {
+  int m0, mc;          // run of points, from the particle's first point
+  double lo[3], hi[3]; // offset range of the run's points (the whole +-R for one unit)
+  long long nodes;     // nodes of the box planned for the unit (an upper bound)
+};
+
+// box nodes per axis for an offset range of width w (see the device box)
+long long unit_side(double w) { return (long long)floor(w + 1e-6) + 5; }
+
+// largest box (nodes) one workgroup can hold: interpolation (u, flag, list) and spreading
+// (sums, list) per node, 1 KB for the rest
+long long unit_nmax(int dim, size_t cs, int lds_max) {
+  const long long per_node = (long long)std::max<size_t>(dim * cs + 3, dim * cs + 2);
+  return std::min<long long>((lds_max - 1024) / per_node, 65536);
+}
+
+// plan of one particle of diameter D with mc points at offsets offs (4 doubles a point)
+bool plan_particle(int dim, long long nmax, double D, const double* offs, int mc,
+                   std::vector<UnitPlan>& out) {
+  const double R = 0.5 * D;
+  long long full = 1;
+  for (int a = 0; a < dim; a++) full *= unit_side(D);
+  if (2 * full <= nmax && mc <= LDS_THREADS) {
+    UnitPlan u{0, mc, {0, 0, 0}, {0, 0, 0}, full};
+    for (int a = 0; a < dim; a++) {
+      u.lo[a] = -R;
+      u.hi[a] = R;
+    }
+    out.push_back(u);
+    return true;
+  }
+  const int P0 = full <= nmax && mc >= 64 ? (mc + 1) / 2 : mc;
+  for (int P = std::min(P0, LDS_THREADS); P >= 32; P /= 2) {
+    std::vector<UnitPlan> v;
+    bool ok = true;
+    for (int s = 0; s < mc && ok; s += P) {
+      const int e = std::min(mc, s + P);
+      UnitPlan u{s, e - s, {0, 0, 0}, {0, 0, 0}, 1};
+      for (int a = 0; a < dim; a++) {
+        u.lo[a] = 1e300;
+        u.hi[a] = -1e300;
+        for (int k = s; k < e; k++) {
+          const double r = offs[4 * (size_t)k + a];
+          u.lo[a] = std::min(u.lo[a], r);
+          u.hi[a] = std::max(u.hi[a], r);
+        }
+        u.nodes *= unit_side(u.hi[a] - u.lo[a]);
+      }
+      if (u.nodes > nmax) ok = false;
+      v.push_back(u);
+    }
+    if (!ok) continue;
+    out.insert(out.end(), v.begin(), v.end());
+    return true;
+  }
+  return false;
+}
+
+// The units of every particle, the largest box (box_cap) and patch_ok (false when a
+// particle has no plan) are set on the context and copied to the device.
 void build_patches(iblbm_ctx* c) {
   const int dim = c->dim;
-  const size_t cs = c->fp64 ? 8 : 4;
-  // LDS bytes per box node: interpolation (u, flag, list) and spreading (sums, list)
-  const double per_node = std::max<double>((double)(dim * cs + 3), (double)(dim * cs + 2));
-  long long nmax = (long long)((c->lds_max - 1024) / per_node);
-  nmax = std::min<long long>(nmax, 65536);
-  // box nodes per axis for an offset range of width w (see the device box)
-  auto side = [](double w) { return (long long)floor(w + 1e-6) + 5; };
+  const long long nmax = unit_nmax(dim, c->fp64 ? 8 : 4, c->lds_max);
   std::vector<int> own, m0v, mcv;
   std::vector<double> rlo, rhi;
   long long cap = 1;
   bool ok_all = true;
   c->full_side = 0;
   for (int p = 0; p < c->np; p++) {
-    const double D = c->hD[p], R = 0.5 * D;
     const int m0 = c->hstart[p], mc = c->hcount[p];
-    c->full_side = std::max<int>(c->full_side, (int)side(D));
-    long long full = 1;
-    for (int a = 0; a < dim; a++) full *= side(D);
-    if (2 * full <= nmax && mc <= LDS_THREADS) {
-      own.push_back(p);
-      m0v.push_back(m0);
-      mcv.push_back(mc);
-      for (int a = 0; a < 3; a++) {
-        rlo.push_back(a < dim ? -R : 0.0);
-        rhi.push_back(a < dim ? R : 0.0);
-      }
-      cap = std::max(cap, full);
+    c->full_side = std::max<int>(c->full_side, (int)unit_side(c->hD[p]));
+    std::vector<UnitPlan> units;
+    if (!plan_particle(dim, nmax, c->hD[p], &c->hmr[4 * (size_t)m0], mc, units)) {
+      ok_all = false;
       continue;
     }
-    bool done = false;
-    const int P0 = full <= nmax && mc >= 64 ? (mc + 1) / 2 : mc;
-    for (int P = std::min(P0, LDS_THREADS); P >= 32 && !done; P /= 2) {
-      std::vector<int> o2, m2, c2;
-      std::vector<double> l2, h2;
-      long long cap2 = 1;
-      bool ok = true;
-      for (int s = 0; s < mc && ok; s += P) {
-        const int e = std::min(mc, s + P);
-        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int a = 0; a < dim; a++) {
-          lo[a] = 1e300;
-          hi[a] = -1e300;
-          for (int k = s; k < e; k++) {
-            const double r = c->hmr[4 * (size_t)(m0 + k) + a];
-            lo[a] = std::min(lo[a], r);
-            hi[a] = std::max(hi[a], r);
-          }
-        }
-        long long n = 1;
-        for (int a = 0; a < dim; a++) n *= side(hi[a] - lo[a]);
-        if (n > nmax) {
-          ok = false;
-          break;
-        }
-        cap2 = std::max(cap2, n);
-        o2.push_back(p);
-        m2.push_back(m0 + s);
-        c2.push_back(e - s);
-        for (int a = 0; a < 3; a++) {
-          l2.push_back(lo[a]);
-          h2.push_back(hi[a]);
-        }
+    for (const UnitPlan& u : units) {
+      own.push_back(p);
+      m0v.push_back(m0 + u.m0);
+      mcv.push_back(u.mc);
+      for (int a = 0; a < 3; a++) {
+        rlo.push_back(u.lo[a]);
+        rhi.push_back(u.hi[a]);
       }
-      if (!ok) continue;
-      own.insert(own.end(), o2.begin(), o2.end());
-      m0v.insert(m0v.end(), m2.begin(), m2.end());
-      mcv.insert(mcv.end(), c2.begin(), c2.end());
-      rlo.insert(rlo.end(), l2.begin(), l2.end());
-      rhi.insert(rhi.end(), h2.begin(), h2.end());
-      cap = std::max(cap, cap2);
-      done = true;
+      cap = std::max(cap, u.nodes);
     }
-    if (!done) ok_all = false;
   }
   int* ip[] = {c->pt_owner, c->pt_m0, c->pt_mc};
   for (int* q : ip)
@@ -943,6 +953,35 @@ iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
     return IBLBM_OK;
   }
   return fail(c, IBLBM_E_ARG, "unknown option");
+}
+
+iblbm_status iblbm_plan_units(int32_t dim, int32_t storage, int32_t lds_bytes, double diameter,
+                              int32_t n_points, int32_t cap, int32_t* n_units, int32_t* first,
+                              int32_t* count, int64_t* box_nodes) {
+  if ((dim != 2 && dim != 3) || storage < IBLBM_F64 || storage > IBLBM_F16 || lds_bytes < 0 ||
+      !(diameter > 0.0 && diameter <= 4096.0) || n_points < 0 || n_points > (1 << 24) ||
+      cap < 0 || !n_units)
+    return IBLBM_E_ARG;
+  const int lds = lds_bytes > 0 ? lds_bytes : 160 * 1024;
+  const int nl = n_points > 0 ? n_points
+                              : (int)floor((dim == 2 ? PI * diameter : PI * diameter * diameter) + 0.5);
+  if (lds <= 1024 || nl < 1 || nl > (1 << 24)) return IBLBM_E_ARG;
+  try {
+    std::vector<double> offs;
+    marker_offsets(dim, 0.5 * diameter, nl, offs);
+    std::vector<UnitPlan> units;
+    const bool ok = plan_particle(dim, unit_nmax(dim, storage == IBLBM_F64 ? 8 : 4, lds), diameter,
+                                  offs.data(), nl, units);
+    *n_units = ok ? (int32_t)units.size() : 0;
+    for (int u = 0; ok && u < (int)units.size() && u < cap; u++) {
+      if (first) first[u] = units[u].m0;
+      if (count) count[u] = units[u].mc;
+      if (box_nodes) box_nodes[u] = units[u].nodes;
+    }
+  } catch (const std::bad_alloc&) {
+    return IBLBM_E_NOMEM;
+  }
+  return IBLBM_OK;
 }
 
 iblbm_status iblbm_set_graph(iblbm_ctx* c, int32_t on) {

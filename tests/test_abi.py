@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -73,3 +74,75 @@ def test_create_rejects_bad_config_without_gpu():
     cfg.struct_size = 8
     h = ctypes.c_void_p()
     assert binding.lib().iblbm_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+
+
+def _plan(*args, **kw):
+    from paper_2002_08855_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libiblbm.so not built")
+    return binding.plan_units(*args, **kw)
+
+
+@pytest.mark.parametrize("dim,storage,D,npts,units", [
+    # 21^3 box of FP32 sums: fits one workgroup's 160 KB but not two, so two bands
+    (3, "f32", 16.0, 804, [(0, 402), (402, 402)]),
+    # 17^3 box fits twice: one unit (16-bit storage computes in FP32 too)
+    (3, "f32", 12.0, 452, [(0, 452)]),
+    (3, "bf16", 12.0, 452, [(0, 452)]),
+    (3, "f64", 12.0, 452, [(0, 226), (226, 226)]),
+    (3, "f64", 10.0, 314, [(0, 157), (157, 157)]),
+    # more points than a workgroup's 1024 lanes
+    (2, "f64", 40.0, 2000, [(0, 1000), (1000, 1000)]),
+    (2, "f32", 20.4, 64, [(0, 64)]),
+    # FP64 bands of a D = 36 sphere stay wider than one workgroup's LDS: point-wise kernels
+    (3, "f64", 36.0, 0, []),
+])
+def test_plan_units_cases(dim, storage, D, npts, units):
+    """Host-side plan of the per-particle work units: whole particles, two bands, runs
+    of at most a workgroup's points, or no plan."""
+    assert [(f, c) for f, c, _ in _plan(dim, storage, D, npts)] == units
+
+
+@pytest.mark.parametrize("dim,storage,D,npts", [
+    (3, "f32", 16.0, 804), (3, "f64", 28.0, 0), (3, "f32", 30.0, 0), (3, "f64", 12.0, 452),
+    (2, "f64", 40.0, 2000), (2, "f32", 48.0, 0), (3, "f32", 20.0, 0)])
+def test_plan_units_cover_every_support(dim, storage, D, npts):
+    """The units split the points into consecutive runs that cover each point once; each
+    unit's box fits one workgroup's LDS; and it holds the union of the 4-point supports
+    (Eqs. 47-48) of its points, placed by the oracle's own point generator, for centres
+    at several sub-node offsets."""
+    import oracle
+    from paper_2002_08855_amd import inputs
+    plan = _plan(dim, storage, D, npts)
+    n = npts or int(np.floor((np.pi * D if dim == 2 else np.pi * D * D) + 0.5))
+    assert plan and plan[0][0] == 0
+    for (f0, c0, _), (f1, _, _) in zip(plan, plan[1:]):
+        assert f1 == f0 + c0
+    assert plan[-1][0] + plan[-1][1] == n
+    cs = 8 if storage == "f64" else 4
+    assert all(nodes * (dim * cs + 3) + 1024 <= 160 * 1024 for _, _, nodes in plan)
+    side = int(D) + 24
+    p = inputs.default_params(dim, (side,) * dim, storage="f64")
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        c = np.array([side / 2 + rng.uniform(-0.5, 0.5) for _ in range(dim)] + [0.0] * (3 - dim))
+        o = oracle.Sim(p)
+        o.add_particles(c[None, :], [D], [1.5], n_markers=n)
+        X = (c[None, :] + o.markers()["r"])[:, :dim]  # r: offsets from the centre
+        o.close()
+        for f, cnt, nodes in plan:
+            pts = X[f:f + cnt]
+            width = np.floor(pts.max(0)) - np.floor(pts.min(0)) + 4
+            assert np.prod(width) <= nodes, (f, cnt, width, nodes)
+
+
+def test_plan_units_rejects_bad_arguments():
+    from paper_2002_08855_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libiblbm.so not built")
+    n = ctypes.c_int32()
+    L = binding.lib()
+    for args in ((4, 1, 0, 10.0, 0), (3, 7, 0, 10.0, 0), (3, 1, 0, 0.0, 0), (3, 1, 0, -2.0, 0),
+                 (3, 1, 0, 10.0, -1), (3, 1, 512, 10.0, 0), (2, 0, 0, float("nan"), 0)):
+        assert L.iblbm_plan_units(*args, 0, ctypes.byref(n), None, None, None) == 1, args
+    assert L.iblbm_plan_units(3, 1, 0, 10.0, 0, 0, None, None, None, None) == 1
