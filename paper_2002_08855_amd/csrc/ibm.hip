@@ -424,33 +424,6 @@ constexpr int LIST_BATCH = 4;
 
 // The vector of a node (ustar, facc): vd consecutive values, 2 in 2-D and 4 in 3-D,
 // loaded as one aligned vector.
-template <class C, int DIM>
-struct NodeVec;
-template <>
-struct NodeVec<float, 2> {
-  using T = float2;
-};
-template <>
-struct NodeVec<float, 3> {
-  using T = float4;
-};
-template <>
-struct NodeVec<double, 2> {
-  using T = double2;
-};
-template <>
-struct NodeVec<double, 3> {
-  using T = double4;
-};
-template <int DIM, class C>
-__device__ __forceinline__ typename NodeVec<C, DIM>::T load_node(const C* v, size_t i) {
-  return *reinterpret_cast<const typename NodeVec<C, DIM>::T*>(v + i);
-}
-template <class C, class V>
-__device__ __forceinline__ C comp(const V& v, int c) {
-  return reinterpret_cast<const C*>(&v)[c];
-}
-
 // 1-D weights of a point's support (the factors of Eq. 12).  With f the offset of X
 // past its first support node (Peskin 4-point) or from its nearest node (Roma
 // 3-point) and s the one square root both kernels need, the weight of support node q
@@ -674,9 +647,8 @@ __global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
     const int t = tl[j];
     int x, y, z;
     b.at(t, x, y, z);
-    C* fa = a.facc + (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
-#pragma unroll
-    for (int c = 0; c < DIM; c++) fa[c] = C(0);
+    const C zero[3] = {C(0), C(0), C(0)};
+    store_node<DIM>(a.facc, (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd, zero);
   }
   band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
 }
@@ -757,11 +729,10 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
       C S, u[3];
       moments<DIM, C>(f, a.geo.rho0, S, u);
 #pragma unroll
-      for (int c = 0; c < DIM; c++) {
-        ub[c * a.cap + t] = u[c];
-        a.ustar[i + c] = u[c];
-        a.facc[i + c] = C(0);
-      }
+      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = u[c];
+      store_node<DIM>(a.ustar, i, u);
+      const C zero[3] = {C(0), C(0), C(0)};
+      store_node<DIM>(a.facc, i, zero);
     }
   } else {
     // u* + F / (2 rho0) at the listed nodes, LIST_BATCH entries per lane at a time

@@ -274,9 +274,7 @@ __global__ __launch_bounds__(256) void k_ustar_all(InteriorArgs<typename Store<T
     load_all<DIM, T, PAR>(slot, a.g, x, y, z, i, a.inv_s, f);
   C S, u[3];
   moments<DIM, C>(f, a.g.rho0, S, u);
-  C* us = const_cast<C*>(a.ustar) + (size_t)i * a.vd;
-#pragma unroll
-  for (int c = 0; c < DIM; c++) us[c] = u[c];
+  store_node<DIM>(const_cast<C*>(a.ustar), (size_t)i * a.vd, u);
 }
 
 // Momentum and angular momentum of the fluid inside each particle volume,

@@ -280,3 +280,42 @@ void dispatch(iblbm_ctx* c, Args... args) {
 }
 
 }  // namespace pdf
+
+template <class C, int DIM>
+struct NodeVec;
+template <>
+struct NodeVec<float, 2> {
+  using T = float2;
+};
+template <>
+struct NodeVec<float, 3> {
+  using T = float4;
+};
+template <>
+struct NodeVec<double, 2> {
+  using T = double2;
+};
+template <>
+struct NodeVec<double, 3> {
+  using T = double4;
+};
+template <int DIM, class C>
+__device__ __forceinline__ typename NodeVec<C, DIM>::T load_node(const C* v, size_t i) {
+  return *reinterpret_cast<const typename NodeVec<C, DIM>::T*>(v + i);
+}
+template <class C, class V>
+__device__ __forceinline__ C comp(const V& v, int c) {
+  return reinterpret_cast<const C*>(&v)[c];
+}
+
+// whole-node store of the first DIM values of x (the padding of a 3-D node gets zero), so
+// that nodes are written as full vectors rather than one component at a time
+template <int DIM, class C>
+__device__ __forceinline__ void store_node(C* v, size_t i, const C* x) {
+  typename NodeVec<C, DIM>::T w;
+  C* e = reinterpret_cast<C*>(&w);
+#pragma unroll
+  for (int c = 0; c < (int)(sizeof(w) / sizeof(C)); c++) e[c] = c < DIM ? x[c] : C(0);
+  *reinterpret_cast<typename NodeVec<C, DIM>::T*>(v + i) = w;
+}
+
