@@ -115,7 +115,7 @@ struct iblbm_ctx {
   void* f = nullptr;        // (q-1) x N, storage type
   void* ustar = nullptr;    // band u*, N x VD compute type
   void* facc = nullptr;     // IB force density, N x VD compute type
-  int vd = 2;               // vector stride of ustar / facc (2 in 2-D, 4 in 3-D)
+  int vd = 2;               // vector stride of ustar / facc (2 in 2-D, 3 in 3-D, packed)
   uint32_t* bmap = nullptr;   // 2 x nwords band bitmaps (bit per node), one per step parity
   long long nwords = 0, nwx = 0;  // words per bitmap, 32-node words per row
   int fbuf = 0;               // bitmap of the most recent step

@@ -465,7 +465,7 @@ iblbm_status iblbm_create(const iblbm_config* cfg, iblbm_ctx** out) {
   c->storage = cfg->storage;
   c->fp64 = cfg->storage == IBLBM_F64;
   c->sbytes = cfg->storage == IBLBM_F64 ? 8 : (cfg->storage == IBLBM_F32 ? 4 : 2);
-  c->vd = c->dim == 2 ? 2 : 4;
+  c->vd = c->dim == 2 ? 2 : 3;
   try {
     HIPCHK(hipGetDevice(&c->device));
     HIPCHK(hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));

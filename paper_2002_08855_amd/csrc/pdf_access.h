@@ -287,9 +287,18 @@ template <>
 struct NodeVec<float, 2> {
   using T = float2;
 };
+// 3-D nodes of u* and the force are packed 12-byte (24-byte in FP64) triples: a 64-byte
+// line holds 16 useful words rather than the 12 of a padded float4 layout, which cuts the
+// line requests of the spreading flush's atomics and of the staging loads
+struct Node3f {
+  float v[3];
+};
+struct Node3d {
+  double v[3];
+};
 template <>
 struct NodeVec<float, 3> {
-  using T = float4;
+  using T = Node3f;
 };
 template <>
 struct NodeVec<double, 2> {
@@ -297,7 +306,7 @@ struct NodeVec<double, 2> {
 };
 template <>
 struct NodeVec<double, 3> {
-  using T = double4;
+  using T = Node3d;
 };
 template <int DIM, class C>
 __device__ __forceinline__ typename NodeVec<C, DIM>::T load_node(const C* v, size_t i) {
@@ -308,14 +317,14 @@ __device__ __forceinline__ C comp(const V& v, int c) {
   return reinterpret_cast<const C*>(&v)[c];
 }
 
-// whole-node store of the first DIM values of x (the padding of a 3-D node gets zero), so
-// that nodes are written as full vectors rather than one component at a time
+// whole-node store of the DIM values of x, so that a node is written by one store rather
+// than one component at a time
 template <int DIM, class C>
 __device__ __forceinline__ void store_node(C* v, size_t i, const C* x) {
   typename NodeVec<C, DIM>::T w;
   C* e = reinterpret_cast<C*>(&w);
 #pragma unroll
-  for (int c = 0; c < (int)(sizeof(w) / sizeof(C)); c++) e[c] = c < DIM ? x[c] : C(0);
+  for (int c = 0; c < DIM; c++) e[c] = x[c];
   *reinterpret_cast<typename NodeVec<C, DIM>::T*>(v + i) = w;
 }
 
