@@ -422,8 +422,6 @@ __device__ __forceinline__ void unit_of(const LdsArgs<C>& a, int q, int& p, int&
 // latencies overlap.
 constexpr int LIST_BATCH = 4;
 
-// The vector of a node (ustar, facc): vd consecutive values, 2 in 2-D and 4 in 3-D,
-// loaded as one aligned vector.
 // 1-D weights of a point's support (the factors of Eq. 12).  With f the offset of X
 // past its first support node (Peskin 4-point) or from its nearest node (Roma
 // 3-point) and s the one square root both kernels need, the weight of support node q
@@ -590,7 +588,10 @@ __device__ inline int list_flags(const uint8_t* flag, int n, uint16_t* out, int*
 }
 
 // Set the flagged nodes of a particle's box in the band bitmap, one lane per box row and
-// one atomic per (row, 32-node word).
+// one atomic per (row, 32-node word).  A row of the box spans any number of words: the
+// lane walks the row in x order and flushes each word's mask when the next word begins.
+// Flagged nodes lie inside the walls (the supports skip wall nodes), so x stays in
+// [0, n0) and the word stays inside the row.
 template <int DIM>
 __device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b,
                                           const uint8_t* flag, uint32_t* bmap, int nwx) {
@@ -598,17 +599,22 @@ __device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b
   for (int r = threadIdx.x; r < rows; r += blockDim.x) {
     int y = b.lo[1] + r % b.B[1], z = b.lo[2] + r / b.B[1];
     if (y < 0 || y >= g.n[1] || z < 0 || z >= g.n[2]) continue;
-    int w0 = (b.lo[0] >= 0 ? b.lo[0] : 0) >> 5;
-    uint32_t m[3] = {0u, 0u, 0u};
+    uint32_t* row = bmap + (size_t)nwx * (y + g.n[1] * z);
+    int wcur = -1;
+    uint32_t m = 0u;
     for (int xl = 0; xl < b.B[0]; xl++) {
       if (!flag[xl + b.B[0] * r]) continue;
-      int x = b.lo[0] + xl;
-      int wi = (x >> 5) - w0;
-      if (wi >= 0 && wi < 3) m[wi] |= 1u << (x & 31);
+      const int x = b.lo[0] + xl;
+      if (x < 0 || x >= g.n[0]) continue;
+      const int wi = x >> 5;
+      if (wi != wcur) {
+        if (m) atomicOr(row + wcur, m);
+        wcur = wi;
+        m = 0u;
+      }
+      m |= 1u << (x & 31);
     }
-    uint32_t* row = bmap + (size_t)nwx * (y + g.n[1] * z);
-    for (int wi = 0; wi < 3; wi++)
-      if (m[wi]) atomicOr(row + w0 + wi, m[wi]);
+    if (m) atomicOr(row + wcur, m);
   }
 }
 

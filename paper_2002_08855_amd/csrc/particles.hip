@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_pairs(PartArgs a) {
   }
   for (int d = 0; d < 3; d++) a.Fc[3 * i + d] = F[d];
   a.pair_nup[i] = min(nup, PAIR_CAP);
+  a.pair_nall[i] = min(cnt, PAIR_CAP);
   if (over || ncand > MAXP) atomicOr(a.status, ST_PAIR_OVERFLOW);
 }
 

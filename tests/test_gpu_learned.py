@@ -100,6 +100,31 @@ def _sim_pair(params, X, D, rho, nm=452):
     return g, o
 
 
+def test_capture_samples_gap_feature_near_neighbours_and_walls():
+    """The gap feature where it is not clamped: two spheres 0.6 lu apart and two spheres
+    0.3 and 0.2 lu from a wall.  The gap column falls below zeta on those points and
+    matches the oracle, which takes it from the pair partners and the wall planes."""
+    X = np.array([[14.0, 14.0, 14.0], [26.6, 14.2, 13.9], [5.8, 30.0, 30.0], [30.0, 30.0, 37.3]])
+    D = np.full(4, 12.0)
+    rho = np.full(4, 2.0)
+    p = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f64", mdf_iters=3)
+    g, o = _sim_pair(p, X, D, rho)
+    for s in (g, o):
+        s.step(4)
+    fg, _ = g.capture_samples()
+    fo, _ = o.capture_samples()
+    gap_g, gap_o = fg[:, 9], fo[:, 9]
+    nm = 452
+    print("min gap per sphere", [float(gap_o[k * nm:(k + 1) * nm].min()) for k in range(4)])
+    # every sphere has points closer than zeta = 1 to a neighbour or a wall
+    for k in range(4):
+        assert gap_o[k * nm:(k + 1) * nm].min() < 0.7
+    assert np.sum(gap_o < 0.99) > 20
+    e = np.abs(gap_g - gap_o).max()
+    print("gap max abs err", e)
+    assert e < 1e-6
+
+
 def test_capture_samples_matches_oracle():
     """Features at the start of a step and the converged MDF-5 force, GPU vs oracle."""
     X, D, rho = _cavity()
