@@ -228,6 +228,20 @@ iblbm_status iblbm_nn_train(const float* x, const float* t, int64_t n, float* pa
 /* Loss and gradient of the MSE loss at params on (x, t) computed on the GPU in FP32. */
 iblbm_status iblbm_nn_grad(const float* x, const float* t, int64_t n, const float* params,
                            float* loss, float* grad);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid allocation): iblbm_nn_grad on
+ * DEVICE arrays, enqueued on `stream` (a hipStream_t, NULL for the null stream) without
+ * synchronising.  x (n*10), t (n*3) and params (5059) are device inputs; loss (1 float)
+ * and grad (5059) are device outputs, written by the same kernels as iblbm_nn_grad (the
+ * loss as the FP64 sum of the same per-block partials).  The activations live in a fixed
+ * scratch array of 8.6 MB that the library holds on each device until the process
+ * ends: n may not exceed IBLBM_NOALLOC_MAX_SAMPLES (IBLBM_E_CAPACITY), and no
+ * allocation or free happens in the call.  Calls that overlap on one device share that
+ * scratch and race: serialise them (one stream, or events).  IBLBM_E_ARG for NULL
+ * pointers or n <= 0; IBLBM_E_DEVICE if a HIP call fails. */
+#define IBLBM_NOALLOC_MAX_SAMPLES 8192
+iblbm_status iblbm_nn_grad_noalloc(const float* x, const float* t, int64_t n, const float* params,
+                                   float* loss, float* grad, void* stream);
 /* Forward pass on the GPU with BF16 weights/activations on MFMA, FP32 accumulation. */
 iblbm_status iblbm_nn_forward(const float* x, int64_t n, const float* params, float* y);
 

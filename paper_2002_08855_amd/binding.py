@@ -100,6 +100,7 @@ def lib():
             "iblbm_nn_train": (C.c_int, [_f, _f, C.c_int64, _f, _P(TrainOpts), _f]),
             "iblbm_nn_grad": (C.c_int, [_f, _f, C.c_int64, _f, _f, _f]),
             "iblbm_nn_forward": (C.c_int, [_f, C.c_int64, _f, _f]),
+            "iblbm_nn_grad_noalloc": (C.c_int, [vp, vp, C.c_int64, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -366,6 +367,13 @@ def nn_grad(params, x, t):
     _raise(lib().iblbm_nn_grad(_fp(x), _fp(t), x.shape[0], _fp(_f32(params)), _fp(loss), _fp(g)),
            "nn_grad")
     return float(loss[0]), g
+
+
+def nn_grad_noalloc(x_ptr, t_ptr, n, params_ptr, loss_ptr, grad_ptr, stream=None):
+    """iblbm_nn_grad_noalloc on device addresses (ints, e.g. torch tensor data_ptr());
+    enqueued on `stream` (a hipStream_t as int, None for the null stream)."""
+    _raise(lib().iblbm_nn_grad_noalloc(x_ptr, t_ptr, int(n), params_ptr, loss_ptr, grad_ptr,
+                                       stream), "nn_grad_noalloc")
 
 
 def nn_train(x, t, params, epochs=10, batch=4096, lr=1e-3, seed=0, check_fp32=False):

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -407,6 +408,46 @@ void run_features(iblbm_ctx* c) {
   hipLaunchKernelGGL(k_features, dim3((c->nmk + 255) / 256), dim3(256), 0, c->stream, a);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free gradient entry point: the activations
+// Z1, Z2 (tanh outputs), dH1, dH2 (n x 64 each), Y, dY (n x 3) and the per-block partial
+// losses of up to NOALLOC_MAX samples, 8.6 MB.  Each device holds its own copy for the
+// life of the process.  In host code `scratch` is only a stand-in symbol: its device
+// address comes from hipGetSymbolAddress, once per device, and only that address is
+// handed to kernels.
+constexpr int NOALLOC_MAX = 8192;
+constexpr size_t NOALLOC_PARTS = ((size_t)NOALLOC_MAX * NO + 255) / 256;
+constexpr size_t NOALLOC_FLOATS =
+    4 * (size_t)NOALLOC_MAX * NH + 2 * (size_t)NOALLOC_MAX * NO + ((NOALLOC_PARTS + 63) & ~(size_t)63);
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_ptr[MAX_DEVICES] = {nullptr};
+
+// device address of this device's scratch (looked up on the first call on the device)
+hipError_t scratch_of_device(int dev, float** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = (float*)p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// mean squared error from the per-block partial sums, summed in block order in FP64 as
+// the host does for iblbm_nn_grad
+__global__ void k_loss_total(const float* part, int parts, double count, float* loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0;
+  for (int i = 0; i < parts; i++) t += part[i];
+  *loss = float(t / count);
+}
+
 }  // namespace
 
 // Learned forcing stage of one step (after the cells/pairs and the band request):
@@ -549,6 +590,41 @@ iblbm_status iblbm_nn_grad(const float* x, const float* t, int64_t n, const floa
   if (loss) *loss = read_loss(s, net, (int)n);
   if (grad && hipMemcpy(grad, net.G, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return IBLBM_E_DEVICE;
+  return IBLBM_OK;
+}
+
+iblbm_status iblbm_nn_grad_noalloc(const float* x, const float* t, int64_t n, const float* params,
+                                   float* loss, float* grad, void* stream) {
+  if (!x || !t || !params || !loss || !grad || n <= 0) return IBLBM_E_ARG;
+  if (n > NOALLOC_MAX) return IBLBM_E_CAPACITY;
+  int dev = 0;
+  float* base = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || scratch_of_device(dev, &base) != hipSuccess)
+    return IBLBM_E_DEVICE;
+  const int B = (int)n;
+  Net net;
+  net.B = B;
+  net.P = const_cast<float*>(params);  // read only: fwd_bwd writes gradients to net.G
+  net.G = grad;
+  float* q = base;
+  net.Z1 = q;
+  q += (size_t)B * NH;
+  net.Z2 = q;
+  q += (size_t)B * NH;
+  net.dH1 = q;
+  q += (size_t)B * NH;
+  net.dH2 = q;
+  q += (size_t)B * NH;
+  net.Y = q;
+  q += (size_t)B * NO;
+  net.dY = q;
+  q += (size_t)B * NO;
+  net.loss_part = q;
+  hipStream_t s = (hipStream_t)stream;
+  fwd_bwd(s, net, x, t, B);
+  const int parts = (B * NO + 255) / 256;
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, net.loss_part, parts, double(B) * NO, loss);
+  if (hipGetLastError() != hipSuccess) return IBLBM_E_DEVICE;
   return IBLBM_OK;
 }
 
