@@ -49,12 +49,10 @@ _d = _P(C.c_double)
 _i32 = _P(C.c_int32)
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = C.CDLL(LIB_PATH)
+def load(path):
+    """A ctypes handle of an oracle library at `path`, with the signatures set."""
+    L = C.CDLL(path)
+    if True:
         sig = {
             "ref_lattice": (C.c_int32, [C.c_int32, _i32, _d]),
             "ref_feq": (None, [C.c_int32, C.c_double, C.c_double, _d, _d]),
@@ -92,12 +90,29 @@ def lib():
             "ref_mlp_loss_grad": (C.c_double, [_d, C.c_int64, _d, _d, _d]),
             "ref_set_mlp": (C.c_int32, [C.c_void_p, _d, _d]),
             "ref_capture_samples": (C.c_int32, [C.c_void_p, _d, _d]),
+            "ref_particle_loads": (None, [C.c_int32, _d, _d, _d, _d, _d]),
+            "ref_interior_momentum": (None, [C.c_int32, _i32, _d, C.c_double, C.c_double, _d, _d,
+                                             _d]),
+            "ref_newton_euler": (None, [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]
+                                 + [_d] * 13),
+            "ref_pair_forces": (None, [C.c_int32, _i32, _i32, C.c_int32, _d, _d, _d, C.c_double,
+                                       C.c_double, C.c_double, _i32, C.c_int64, _d]),
+            "ref_point_gap": (C.c_double, [C.c_int32, _i32, _i32, C.c_double, _d, C.c_int32, _d,
+                                           _d, _i32, C.c_int64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = L
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = load(LIB_PATH)
     return _lib
 
 
@@ -223,6 +238,62 @@ def mlp_loss_grad(params, x, t):
     g = np.zeros(NPARAM)
     loss = lib().ref_mlp_loss_grad(_dp(params), x.shape[0], _dp(x), _dp(t), _dp(g))
     return loss, g
+
+
+# ---- particle coupling (Sec. 2.3) ---------------------------------------------
+# Each takes an optional library handle L (from load()); the default is this package's.
+
+def particle_loads(r, F, dV, L=None):
+    r = _f64(r, (-1, 3))
+    F = _f64(F, (-1, 3))
+    dV = _f64(dV)
+    Fh, Th = np.zeros(3), np.zeros(3)
+    (L or lib()).ref_particle_loads(r.shape[0], _dp(r), _dp(F), _dp(dV), _dp(Fh), _dp(Th))
+    return Fh, Th
+
+
+def interior_momentum(dim, n, Xc, R, rho0, u, L=None):
+    n = np.asarray(list(n) + [1] * (3 - len(n)), np.int32)
+    Xc = _f64(np.resize(np.asarray(Xc, float), 3))
+    u = _f64(u)
+    P, Lm = np.zeros(3), np.zeros(3)
+    (L or lib()).ref_interior_momentum(dim, _ip(n), _dp(Xc), float(R), float(rho0), _dp(u), _dp(P),
+                                       _dp(Lm))
+    return P, Lm
+
+
+def newton_euler(dim, M, V, I, rho0, g, Fh, Th, Fc, P, Lm, state, L=None):
+    """One step of Eqs. 14-15 for one particle.  `state` is a dict of 3-vectors Pprev,
+    Lprev, Hprev, Gprev, X, U, Om, updated in place (and returned)."""
+    args = [_f64(np.resize(np.asarray(a, float), 3)) for a in (g, Fh, Th, Fc, P, Lm)]
+    for k in ("Pprev", "Lprev", "Hprev", "Gprev", "X", "U", "Om"):
+        state[k] = _f64(np.resize(np.asarray(state[k], float), 3)).copy()
+    (L or lib()).ref_newton_euler(dim, float(M), float(V), float(I), float(rho0),
+                                  *[_dp(a) for a in args],
+                                  *[_dp(state[k]) for k in ("Pprev", "Lprev", "Hprev", "Gprev", "X",
+                                                            "U", "Om")])
+    return state
+
+
+def pair_forces(dim, n, periodic, X, D, c, zeta, eps_pp, E_pp, pairs, L=None):
+    n = np.asarray(list(n) + [1] * (3 - len(n)), np.int32)
+    per = np.asarray(periodic, np.int32)
+    X = _f64(X, (-1, 3))
+    ij = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    Fc = np.zeros((X.shape[0], 3))
+    (L or lib()).ref_pair_forces(dim, _ip(n), _ip(per), X.shape[0], _dp(X), _dp(_f64(D)),
+                                 _dp(_f64(c)), zeta, eps_pp, E_pp, _ip(ij), ij.shape[0], _dp(Fc))
+    return Fc
+
+
+def point_gap(dim, n, periodic, zeta, Xk, p, X, D, pairs, L=None):
+    n = np.asarray(list(n) + [1] * (3 - len(n)), np.int32)
+    per = np.asarray(periodic, np.int32)
+    Xk = _f64(np.resize(np.asarray(Xk, float), 3))
+    X = _f64(X, (-1, 3))
+    ij = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    return (L or lib()).ref_point_gap(dim, _ip(n), _ip(per), zeta, _dp(Xk), int(p), _dp(X),
+                                      _dp(_f64(D)), _ip(ij), ij.shape[0])
 
 
 # ---- the time-stepping context ----------------------------------------------

@@ -929,144 +929,178 @@ static void apply_face_bc(ref_ctx* c) {
   }
 }
 
-static void particle_loads(ref_ctx* c) {
-  /* F_h = -sum F_k dV_k and T_h = -sum r_k x F_k dV_k (reaction of the IB force) */
-  for (int p = 0; p < c->np; p++) {
-    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-    for (int m = c->mstart[p]; m < c->mstart[p] + c->mcount[p]; m++) {
-      const double* r = c->mr + 3 * m;
-      const double* Fk = c->mF + 3 * m;
-      double dV = c->mdV[m];
-      double Fd[3] = {Fk[0] * dV, Fk[1] * dV, Fk[2] * dV};
-      double t[3] = {r[1] * Fd[2] - r[2] * Fd[1], r[2] * Fd[0] - r[0] * Fd[2],
-                     r[0] * Fd[1] - r[1] * Fd[0]};
-      for (int a = 0; a < 3; a++) {
-        F[a] = F[a] - Fd[a];
-        T[a] = T[a] - t[a];
-      }
-    }
+/* Hydrodynamic load of one particle (Sec. 2.3, the reaction of the IB force of Eqs. 10
+ * and 13): F_h = -sum_k F_k dV_k and T_h = -sum_k r_k x (F_k dV_k) over its points k in
+ * ascending order; r_k and F_k are nmk x 3. */
+void ref_particle_loads(int32_t nmk, const double* r, const double* Fk, const double* dV,
+                        double* Fh, double* Th) {
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  for (int m = 0; m < nmk; m++) {
+    const double* rk = r + 3 * m;
+    const double* f = Fk + 3 * m;
+    double Fd[3] = {f[0] * dV[m], f[1] * dV[m], f[2] * dV[m]};
+    double t[3] = {rk[1] * Fd[2] - rk[2] * Fd[1], rk[2] * Fd[0] - rk[0] * Fd[2],
+                   rk[0] * Fd[1] - rk[1] * Fd[0]};
     for (int a = 0; a < 3; a++) {
-      c->Fh[3 * p + a] = F[a];
-      c->Th[3 * p + a] = T[a];
+      F[a] = F[a] - Fd[a];
+      T[a] = T[a] - t[a];
     }
   }
+  for (int a = 0; a < 3; a++) {
+    Fh[a] = F[a];
+    Th[a] = T[a];
+  }
+}
+
+static void particle_loads(ref_ctx* c) {
+  for (int p = 0; p < c->np; p++) {
+    int m0 = c->mstart[p];
+    ref_particle_loads(c->mcount[p], c->mr + 3 * m0, c->mF + 3 * m0, c->mdV + m0, c->Fh + 3 * p,
+                       c->Th + 3 * p);
+  }
+}
+
+/* Pair forces F_c (Eq. 16) of np particles from their pair list (Table 4: each pair i<j
+ * once, Newton's third law for the partner), then the walls: Eq. 16 against the mirror
+ * image of the particle in each wall plane (planes at -1/2 and n - 1/2, distance 2h
+ * for a centre h from the plane, contact distance D_i, c_i), faces in the order
+ * -x,+x,-y,+y,-z,+z.  c holds the c_i of Eq. 16; pairs use D_ij = (D_i + D_j)/2 and
+ * c_ij = (c_i + c_j)/2. */
+void ref_pair_forces(int32_t dim, const int32_t* n, const int32_t* periodic, int32_t np,
+                     const double* X, const double* D, const double* c, double zeta,
+                     double eps_pp, double E_pp, const int32_t* ij, int64_t npairs, double* Fc) {
+  for (int i = 0; i < 3 * np; i++) Fc[i] = 0.0;
+  for (int64_t m = 0; m < npairs; m++) {
+    int i = ij[2 * m], j = ij[2 * m + 1];
+    double dx[3] = {0, 0, 0}, d2 = 0.0;
+    for (int a = 0; a < dim; a++) {
+      dx[a] = X[3 * i + a] - X[3 * j + a];
+      d2 = d2 + dx[a] * dx[a];
+    }
+    double d = sqrt(d2);
+    double Dij = 0.5 * (D[i] + D[j]);
+    double cij = 0.5 * (c[i] + c[j]);
+    double mag = ref_pair_force(d, Dij, zeta, cij, eps_pp, E_pp);
+    for (int a = 0; a < dim; a++) {
+      double Fa = mag * (dx[a] / d);
+      Fc[3 * i + a] = Fc[3 * i + a] + Fa;
+      Fc[3 * j + a] = Fc[3 * j + a] - Fa;
+    }
+  }
+  for (int p = 0; p < np; p++)
+    for (int a = 0; a < dim; a++) {
+      if (periodic[a]) continue;
+      for (int side = 0; side < 2; side++) {
+        double h = side == 0 ? X[3 * p + a] + 0.5 : (n[a] - 0.5) - X[3 * p + a];
+        double d = 2.0 * h;
+        double mag = ref_pair_force(d, D[p], zeta, c[p], eps_pp, E_pp);
+        if (mag != 0.0) Fc[3 * p + a] = Fc[3 * p + a] + (side == 0 ? mag : -mag);
+      }
+    }
 }
 
 static void pair_forces(ref_ctx* c) {
   const ref_config* k = &c->cfg;
-  for (int i = 0; i < 3 * c->np; i++) c->Fc[i] = 0.0;
-  /* Table 4: each pair once, Newton's third law for the partner */
-  for (int64_t m = 0; m < c->npairs; m++) {
-    int i = c->pairs[2 * m], j = c->pairs[2 * m + 1];
-    double dx[3] = {0, 0, 0}, d2 = 0.0;
-    for (int a = 0; a < c->dim; a++) {
-      dx[a] = c->X[3 * i + a] - c->X[3 * j + a];
-      d2 = d2 + dx[a] * dx[a];
-    }
-    double d = sqrt(d2);
-    double Dij = 0.5 * (c->D[i] + c->D[j]);
-    double cij = 0.5 * (c->cbuoy[i] + c->cbuoy[j]);
-    double mag = ref_pair_force(d, Dij, k->zeta, cij, k->eps_pp, k->E_pp);
-    for (int a = 0; a < c->dim; a++) {
-      double Fa = mag * (dx[a] / d);
-      c->Fc[3 * i + a] = c->Fc[3 * i + a] + Fa;
-      c->Fc[3 * j + a] = c->Fc[3 * j + a] - Fa;
-    }
-  }
-  /* walls: Eq. 16 against the mirror image of the particle in each wall plane
-   * (planes at -1/2 and n - 1/2), faces in the order -x,+x,-y,+y,-z,+z */
-  for (int p = 0; p < c->np; p++)
-    for (int a = 0; a < c->dim; a++) {
-      if (k->periodic[a]) continue;
-      for (int side = 0; side < 2; side++) {
-        double h = side == 0 ? c->X[3 * p + a] + 0.5 : (k->n[a] - 0.5) - c->X[3 * p + a];
-        double d = 2.0 * h;
-        double mag = ref_pair_force(d, c->D[p], k->zeta, c->cbuoy[p], k->eps_pp, k->E_pp);
-        if (mag != 0.0) c->Fc[3 * p + a] = c->Fc[3 * p + a] + (side == 0 ? mag : -mag);
-      }
-    }
+  ref_pair_forces(c->dim, k->n, k->periodic, c->np, c->X, c->D, c->cbuoy, k->zeta, k->eps_pp,
+                  k->E_pp, c->pairs, c->npairs, c->Fc);
 }
 
-/* Momentum and angular momentum of the fluid inside each particle,
- *   P = sum_x chi(x) rho0 u(x),  L = sum_x chi(x) (x - X_c) x rho0 u(x),
- * with u a velocity field (d x N) and chi a volume indicator that falls
+/* Momentum and angular momentum of the fluid inside one particle of radius R centred at
+ * Xc (the fluid that F_f and T_f of Eqs. 14-15 keep moving with the body):
+ *   P = sum_x chi(x) rho0 u(x),  L = sum_x chi(x) (x - Xc) x rho0 u(x),
+ * with u a velocity field (dim x N, component-major) and chi a volume indicator that falls
  * linearly from 1 to 0 across one lattice spacing at the surface:
- * chi = clamp(R + 1/2 - |x - X_c|, 0, 1).  Nodes in x-outer, y, z-inner order. */
-static void interior_momentum(ref_ctx* c, const double* uvel, double* P, double* L) {
-  const ref_config* k = &c->cfg;
-  long N = c->N;
-  for (int p = 0; p < c->np; p++) {
-    const double* Xc = c->X + 3 * p;
-    double R = 0.5 * c->D[p];
-    double Pa[3] = {0, 0, 0}, La[3] = {0, 0, 0};
-    long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    for (int a = 0; a < c->dim; a++) {
-      lo[a] = (long)floor(Xc[a] - R - 0.5);
-      hi[a] = (long)ceil(Xc[a] + R + 0.5);
-      if (lo[a] < 0) lo[a] = 0;
-      if (hi[a] > k->n[a] - 1) hi[a] = k->n[a] - 1;
-    }
-    for (long i = lo[0]; i <= hi[0]; i++)
-      for (long j = lo[1]; j <= hi[1]; j++)
-        for (long l = lo[2]; l <= hi[2]; l++) {
-          double r[3] = {(double)i - Xc[0], (double)j - Xc[1], c->dim == 3 ? (double)l - Xc[2] : 0.0};
-          double d2 = 0.0;
-          for (int a = 0; a < c->dim; a++) d2 = d2 + r[a] * r[a];
-          double chi = R + 0.5 - sqrt(d2);
-          if (chi <= 0.0) continue;
-          if (chi > 1.0) chi = 1.0;
-          long node = i + k->n[0] * (j + (long)k->n[1] * l);
-          double m[3] = {0, 0, 0};
-          for (int a = 0; a < c->dim; a++) m[a] = chi * (k->rho0 * uvel[a * N + node]);
-          double t[3] = {r[1] * m[2] - r[2] * m[1], r[2] * m[0] - r[0] * m[2],
-                         r[0] * m[1] - r[1] * m[0]};
-          for (int a = 0; a < 3; a++) {
-            Pa[a] = Pa[a] + m[a];
-            La[a] = La[a] + t[a];
-          }
+ * chi = clamp(R + 1/2 - |x - Xc|, 0, 1).  Nodes inside the walls, in x-outer, y, z-inner
+ * order. */
+void ref_interior_momentum(int32_t dim, const int32_t* n, const double* Xc, double R, double rho0,
+                           const double* u, double* P, double* L) {
+  long N = (long)n[0] * n[1] * (dim == 3 ? n[2] : 1);
+  double Pa[3] = {0, 0, 0}, La[3] = {0, 0, 0};
+  long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int a = 0; a < dim; a++) {
+    lo[a] = (long)floor(Xc[a] - R - 0.5);
+    hi[a] = (long)ceil(Xc[a] + R + 0.5);
+    if (lo[a] < 0) lo[a] = 0;
+    if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+  }
+  for (long i = lo[0]; i <= hi[0]; i++)
+    for (long j = lo[1]; j <= hi[1]; j++)
+      for (long l = lo[2]; l <= hi[2]; l++) {
+        double r[3] = {(double)i - Xc[0], (double)j - Xc[1], dim == 3 ? (double)l - Xc[2] : 0.0};
+        double d2 = 0.0;
+        for (int a = 0; a < dim; a++) d2 = d2 + r[a] * r[a];
+        double chi = R + 0.5 - sqrt(d2);
+        if (chi <= 0.0) continue;
+        if (chi > 1.0) chi = 1.0;
+        long node = i + n[0] * (j + (long)n[1] * l);
+        double m[3] = {0, 0, 0};
+        for (int a = 0; a < dim; a++) m[a] = chi * (rho0 * u[a * N + node]);
+        double t[3] = {r[1] * m[2] - r[2] * m[1], r[2] * m[0] - r[0] * m[2], r[0] * m[1] - r[1] * m[0]};
+        for (int a = 0; a < 3; a++) {
+          Pa[a] = Pa[a] + m[a];
+          La[a] = La[a] + t[a];
         }
-    for (int a = 0; a < 3; a++) {
-      P[3 * p + a] = Pa[a];
-      L[3 * p + a] = La[a];
-    }
+      }
+  for (int a = 0; a < 3; a++) {
+    P[a] = Pa[a];
+    L[a] = La[a];
+  }
+}
+
+static void interior_momentum(ref_ctx* c, const double* uvel, double* P, double* L) {
+  for (int p = 0; p < c->np; p++)
+    ref_interior_momentum(c->dim, c->cfg.n, c->X + 3 * p, 0.5 * c->D[p], c->cfg.rho0, uvel, P + 3 * p,
+                          L + 3 * p);
+}
+
+/* One step of Eqs. 14-15 for one particle (state X, U, Om updated in place).
+ *   F_b is the buoyant weight (M - rho0 V) g.
+ *   F_f and T_f, which keep the fluid inside the particle moving with it, are the changes
+ *   over the step of the momentum P and angular momentum L of that fluid, taken after
+ *   streaming at consecutive steps: P - Pprev, L - Lprev (dt = 1).  When that fluid
+ *   moves rigidly, P = rho0 V U and Eq. 14 becomes (M - rho0 V) dU/dt = F_h + F_c + F_b.
+ *   Time integration (the paper gives none): the hydrodynamic load H = F_h + F_f (and
+ *   G = T_h + T_f) enters at the middle of the last interval, as the mean of this step's
+ *   and the previous step's values (Hprev, Gprev, zero before the first step), with
+ *   explicit Euler for U and Omega and the trapezoid rule for X:
+ *     U' = U + ((H + Hprev)/2 + F_c + F_b) / M,   Om' = Om + (G + Gprev)/(2 I),
+ *     X' = X + (U + U')/2.
+ * In 2-D only the z component of Omega, T_h and L is used.  Hprev, Gprev, Pprev and Lprev
+ * are replaced by this step's H, G, P and L. */
+void ref_newton_euler(int32_t dim, double M, double V, double I, double rho0, const double* g,
+                      const double* Fh, const double* Th, const double* Fc, const double* P,
+                      const double* L, double* Pprev, double* Lprev, double* Hprev, double* Gprev,
+                      double* X, double* U, double* Om) {
+  double meff = M - rho0 * V;
+  for (int a = 0; a < dim; a++) {
+    double U0 = U[a];
+    double H = Fh[a] + (P[a] - Pprev[a]);
+    double Havg = 0.5 * (H + Hprev[a]);
+    double U1 = U0 + (Havg + Fc[a] + meff * g[a]) / M;
+    Hprev[a] = H;
+    U[a] = U1;
+    X[a] = X[a] + 0.5 * (U0 + U1);
+  }
+  int a0 = dim == 2 ? 2 : 0;
+  for (int a = a0; a < 3; a++) {
+    double G = Th[a] + (L[a] - Lprev[a]);
+    double Gavg = 0.5 * (G + Gprev[a]);
+    Gprev[a] = G;
+    Om[a] = Om[a] + Gavg / I;
+  }
+  for (int a = 0; a < 3; a++) {
+    Pprev[a] = P[a];
+    Lprev[a] = L[a];
   }
 }
 
 static void newton_euler(ref_ctx* c) {
-  /* Eqs. 14-15.  F_b is the buoyant weight (M - rho0 V) g.  F_f and T_f, which keep the
-   * fluid inside the particle moving with it, are the rates of change of the momentum
-   * and angular momentum of the fluid inside the moving particle volume, taken after
-   * streaming at consecutive steps: P^n - P^(n-1), L^n - L^(n-1) (dt = 1).  When that
-   * fluid moves rigidly, P = rho0 V U and Eq. 14 becomes
-   * (M - rho0 V) dU/dt = F_h + F_c + (M - rho0 V) g.
-   * The hydrodynamic load H = F_h + F_f (and G = T_h + T_f) is averaged over the current
-   * and the previous step: the split forcing of Eqs. 7-8 answers a force with an
-   * overshoot one step later, and the two-step average removes the alternating mode
-   * that this feeds when the particle is light.  Explicit Euler for the velocities and
-   * the trapezoid rule for the position. */
   const ref_config* k = &c->cfg;
   for (int p = 0; p < c->np; p++) {
-    double meff = c->M[p] - k->rho0 * c->V[p];
-    for (int a = 0; a < c->dim; a++) {
-      double U0 = c->U[3 * p + a];
-      double H = c->Fh[3 * p + a] + (c->Pin[3 * p + a] - c->Pprev[3 * p + a]);
-      double Havg = 0.5 * (H + c->Hprev[3 * p + a]);
-      double U1 = U0 + (Havg + c->Fc[3 * p + a] + meff * k->gravity[a]) / c->M[p];
-      c->Hprev[3 * p + a] = H;
-      c->U[3 * p + a] = U1;
-      c->X[3 * p + a] = c->X[3 * p + a] + 0.5 * (U0 + U1);
-    }
-    int a0 = c->dim == 2 ? 2 : 0;
-    for (int a = a0; a < 3; a++) {
-      double G = c->Th[3 * p + a] + (c->Lin[3 * p + a] - c->Lprev[3 * p + a]);
-      double Gavg = 0.5 * (G + c->Gprev[3 * p + a]);
-      c->Gprev[3 * p + a] = G;
-      c->Om[3 * p + a] = c->Om[3 * p + a] + Gavg / c->I[p];
-    }
-    for (int a = 0; a < 3; a++) {
-      c->Pprev[3 * p + a] = c->Pin[3 * p + a];
-      c->Lprev[3 * p + a] = c->Lin[3 * p + a];
-    }
+    int s = 3 * p;
+    ref_newton_euler(c->dim, c->M[p], c->V[p], c->I[p], k->rho0, k->gravity, c->Fh + s, c->Th + s,
+                     c->Fc + s, c->Pin + s, c->Lin + s, c->Pprev + s, c->Lprev + s, c->Hprev + s,
+                     c->Gprev + s, c->X + s, c->U + s, c->Om + s);
   }
 }
 
@@ -1305,6 +1339,35 @@ int32_t ref_set_mlp(ref_ctx* c, const double* params, const double* norm) {
   return 0;
 }
 
+/* Gap feature of a surface point Xk of particle p: the distance from Xk to the nearest
+ * surface of a pair partner of p (|Xk - X_o| - D_o/2) or to a wall plane (at -1/2 and
+ * n - 1/2 on non-periodic axes), clamped to [0, zeta].  Only pair partners (centre
+ * distance < D_ij + zeta) can come closer than zeta, so they are the only candidates. */
+double ref_point_gap(int32_t dim, const int32_t* n, const int32_t* periodic, double zeta,
+                     const double* Xk, int32_t p, const double* X, const double* D,
+                     const int32_t* ij, int64_t npairs) {
+  double gap = zeta;
+  for (int64_t s = 0; s < npairs; s++) {
+    int i = ij[2 * s], j = ij[2 * s + 1];
+    int o = i == p ? j : (j == p ? i : -1);
+    if (o < 0) continue;
+    double d2 = 0.0;
+    for (int a = 0; a < dim; a++) {
+      double dx = Xk[a] - X[3 * o + a];
+      d2 = d2 + dx * dx;
+    }
+    double gg = sqrt(d2) - 0.5 * D[o];
+    if (gg < gap) gap = gg;
+  }
+  for (int a = 0; a < dim; a++) {
+    if (periodic[a]) continue;
+    double lo = Xk[a] + 0.5, hi = (n[a] - 0.5) - Xk[a];
+    if (lo < gap) gap = lo;
+    if (hi < gap) gap = hi;
+  }
+  return gap < 0.0 ? 0.0 : gap;
+}
+
 /* Features of each point at the start of the step: slip U_b - D_I u* [3], the point's
  * force of the previous step [3], the outward unit normal r_k/R [3], and the gap to
  * the nearest other surface or wall plane, clamped to [0, zeta] [1].  Only pair
@@ -1322,27 +1385,8 @@ static void features(ref_ctx* c, double* feat) {
       F[3 + a] = c->mFprev[3 * m + a];
       F[6 + a] = c->mr[3 * m + a] / R;
     }
-    double gap = k->zeta;
-    for (int64_t s = 0; s < c->npairs; s++) {
-      int i = c->pairs[2 * s], j = c->pairs[2 * s + 1];
-      int o = i == p ? j : (j == p ? i : -1);
-      if (o < 0) continue;
-      double d2 = 0.0;
-      for (int a = 0; a < c->dim; a++) {
-        double dx = c->mX[3 * m + a] - c->X[3 * o + a];
-        d2 = d2 + dx * dx;
-      }
-      double gg = sqrt(d2) - 0.5 * c->D[o];
-      if (gg < gap) gap = gg;
-    }
-    for (int a = 0; a < c->dim; a++) {
-      if (k->periodic[a]) continue;
-      double lo = c->mX[3 * m + a] + 0.5, hi = (k->n[a] - 0.5) - c->mX[3 * m + a];
-      if (lo < gap) gap = lo;
-      if (hi < gap) gap = hi;
-    }
-    if (gap < 0.0) gap = 0.0;
-    F[9] = gap;
+    F[9] = ref_point_gap(c->dim, k->n, k->periodic, k->zeta, c->mX + 3 * m, p, c->X, c->D,
+                         c->pairs, c->npairs);
   }
 }
 

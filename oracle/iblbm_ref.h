@@ -77,6 +77,35 @@ int64_t ref_half_search(int32_t dim, int32_t np, const double* X, const double* 
 int64_t ref_grid_search(int32_t dim, const int32_t* n, int32_t np, const double* X, const double* D,
                         double zeta, double H, int32_t* ij, int64_t cap);
 
+/* ---- particle coupling (Sec. 2.3): the pieces one step applies per particle ---- */
+/* F_h = -sum F_k dV_k, T_h = -sum r_k x F_k dV_k over nmk points (r, F: nmk*3). */
+void ref_particle_loads(int32_t nmk, const double* r, const double* F, const double* dV,
+                        double* Fh /* 3 */, double* Th /* 3 */);
+/* Momentum P and angular momentum L (3 each) of the fluid inside a particle of radius R
+ * at Xc: sums of chi rho0 u and chi (x - Xc) x rho0 u with chi = clamp(R + 1/2 - |x - Xc|,
+ * 0, 1); u is a dim x N field. */
+void ref_interior_momentum(int32_t dim, const int32_t* n, const double* Xc, double R, double rho0,
+                           const double* u, double* P, double* L);
+/* One Newton-Euler step (Eqs. 14-15) of one particle; every pointer is 3 doubles.  The
+ * hydrodynamic load H = F_h + (P - Pprev) enters as the mean of this and the previous
+ * step's value (Hprev), likewise G = T_h + (L - Lprev) with Gprev; U by explicit Euler with
+ * the buoyant weight (M - rho0 V) g, X by the trapezoid rule.  Pprev, Lprev, Hprev, Gprev,
+ * X, U, Om are updated in place. */
+void ref_newton_euler(int32_t dim, double M, double V, double I, double rho0, const double* g,
+                      const double* Fh, const double* Th, const double* Fc, const double* P,
+                      const double* L, double* Pprev, double* Lprev, double* Hprev, double* Gprev,
+                      double* X, double* U, double* Om);
+/* Eq. 16 pair forces of a pair list (i<j pairs, npairs) and the wall images (distance 2h to
+ * the mirror centre, contact distance D_i) into Fc (np*3); c: c_i of Eq. 16 (np). */
+void ref_pair_forces(int32_t dim, const int32_t* n, const int32_t* periodic, int32_t np,
+                     const double* X, const double* D, const double* c, double zeta,
+                     double eps_pp, double E_pp, const int32_t* ij, int64_t npairs, double* Fc);
+/* Gap feature of surface point Xk of particle p: distance to the nearest surface of a
+ * pair partner or a wall plane, clamped to [0, zeta]. */
+double ref_point_gap(int32_t dim, const int32_t* n, const int32_t* periodic, double zeta,
+                     const double* Xk, int32_t p, const double* X, const double* D,
+                     const int32_t* ij, int64_t npairs);
+
 /* ---- the time-stepping context --------------------------------------- */
 ref_ctx* ref_create(const ref_config* cfg);
 void ref_destroy(ref_ctx* c);
