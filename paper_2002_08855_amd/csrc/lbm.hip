@@ -8,6 +8,7 @@
 // each thread reads and writes the same set of locations and the update is in place
 // and race free.  Links that leave through a wall bounce back half-way with the
 // moving-wall term 2 w_a rho0 (e_a . u_w)/c_s^2.
+#include "index_math.h"
 #include "pdf_access.h"
 
 namespace {
@@ -291,11 +292,8 @@ __global__ __launch_bounds__(256) void k_interior(InteriorArgs<typename Store<T>
   int p = blockIdx.x;
   double Xc[3] = {a.X[3 * p], a.X[3 * p + 1], DIM == 3 ? a.X[3 * p + 2] : 0.0};
   double R = 0.5 * a.D[p];
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; d++) {
-    lo[d] = max(int(floor(Xc[d] - R - 0.5)), 0);
-    hi[d] = min(int(ceil(Xc[d] + R + 0.5)), a.g.n[d] - 1);
-  }
+  int lo[3], hi[3];
+  interior_box(Xc, R, a.g.n, DIM, lo, hi);
   int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
   int total = (wx > 0 && wy > 0 && wz > 0) ? wx * wy * wz : 0;
   if (stop) return;

@@ -9,6 +9,7 @@
 // program; each particle sums its partner forces in ascending partner order, which
 // makes the result independent of thread scheduling.
 #include "common.h"
+#include "index_math.h"
 
 #pragma clang fp contract(off)
 
@@ -29,11 +30,6 @@ struct PartArgs {
   int *pair_all, *pair_nall;
   int* status;
 };
-
-__device__ __forceinline__ int cell_coord(double x, double invh, int nc) {
-  int c = int(floor((x + 0.5) * invh));
-  return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
-}
 
 // Cell of every particle and a slot in it.  Consecutive lanes of a wavefront whose
 // particles share a cell form a run: a ballot of run heads gives every lane its head
