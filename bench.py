@@ -21,35 +21,51 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TIMING_EVERY = 10  # timed region: events on the dominant group's launches of every 10th step
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores, published
+# timed region: events on the dominant group's launches of every 5th step; the stride is
+# odd, so the timed launches fall on both parities of the A-A streaming
+TIMING_EVERY = 5
 GROUPS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
-KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_ustar_all", "interp": "k_interp_lds",
-               "spread": "k_spread_lds", "interior": "k_interior", "particle": "k_pairs"}
+KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_ustar_all + k_mark_lds",
+               "interp": "k_interp_lds", "spread": "k_spread_lds",
+               "interior": "k_interior", "particle": "k_cells + k_pairs + k_loads_newton",
+               "mlp": "k_features + k_mlp_infer"}
+# the kernel of a group whose counter traffic is recorded under profiles/
+PMC_KERNEL = {"collide": "k_collide_stream", "band": "k_ustar_all", "interp": "k_interp_lds",
+              "spread": "k_spread_lds", "interior": "k_interior", "particle": "k_pairs"}
+# MLP 10-64-64-3: 2 (10*64 + 64*64 + 64*3) multiply-adds per point
+MLP_FLOP_PER_POINT = 2 * (10 * 64 + 64 * 64 + 64 * 3)
 
 
 def algorithmic_bytes(group, p, nmk, band_nodes):
-    """Bytes each launch of a kernel group must move (f_0 and padding not credited)."""
+    """Bytes one launch of a kernel group must move, as the survey's measurement section
+    defines them (f_0, padding and the method's own bookkeeping not credited):
+      collide-stream   2 (q-1) s per node + d cs per band node (the force read)
+      band u*          ((q-1) s + d cs) per band node
+      interp + spread  per forcing pass 2 d cs per band node + 16 d per point (offsets in
+                       FP64, U_b and dF); split as interpolation d cs per band node +
+                       12 d per point (u read; offsets, U_b) and spreading d cs per band
+                       node + 4 d per point (f update; dF)
+    with s the stored PDF size and cs the compute size (4 in FP32 as the survey states,
+    8 in FP64).  In 2-D the band u* is made inside the first of the mdf_iters
+    interpolation launches, so each interpolation launch carries 1/mdf_iters of it."""
     dim = p["dim"]
     q = 9 if dim == 2 else 19
     s = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[p["storage"]]
     cs = 8 if p["storage"] == "f64" else 4
     N = p["n"][0] * p["n"][1] * p["n"][2]
+    band = ((q - 1) * s + dim * cs) * band_nodes
     if group == "collide":
-        # read + write of the q-1 live PDFs per node, force read on band nodes
         return 2 * (q - 1) * s * N + dim * cs * band_nodes
-    # u* at the band nodes from their PDFs, written with the cleared force
-    band = (q - 1) * s * band_nodes + 2 * dim * cs * band_nodes
     if group == "band":
         return band
     if group == "interp":
-        # u* and force at band nodes; per point its offset (FP64), owner, F update, dF;
-        # in 2-D the first of the mdf_iters passes also makes the band u* (averaged)
-        b = 2 * dim * cs * band_nodes + nmk * (8 * dim + 4 + 3 * dim * cs)
+        b = dim * cs * band_nodes + nmk * 12 * dim
         if dim == 2:
             b += band / max(1, p["mdf_iters"])
         return b
     if group == "spread":
-        return 2 * dim * cs * band_nodes + nmk * (8 * dim + 4 + 8 + dim * cs)
+        return dim * cs * band_nodes + nmk * 4 * dim
     return None
 
 
@@ -113,7 +129,7 @@ def run(args):
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                 "timed_every_nth_step": TIMING_EVERY,
                 "algorithmic_bytes_per_launch": int(nbytes)}
-        kname = KERNEL_NAME.get(dominant, dominant)
+        kname = PMC_KERNEL.get(dominant, dominant)
         prof = os.path.join(ROOT, "profiles", f"{kname}_{args.workload}_pmc.json")
         if os.path.exists(prof):
             d = json.load(open(prof))
@@ -128,10 +144,9 @@ def run(args):
         roof_collide = {"kernel": "k_collide_stream", "bound": "hbm", "achieved": round(ach_c, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_c / HBM_PEAK_GBS, 4),
                         "avg_launch_ms": round(ms_c, 5), "algorithmic_bytes_per_launch": int(nb_c)}
-    # slip error of the step after the timed region
-    sim.set_stats_every(1)
-    sim.step(1)
-    slip = sim.stats()["slip_rms"]
+    del sim
+    torch.cuda.empty_cache()
+    slip = slip_run(binding, w, int(w.get("steps", 500)))
     out = {
         "metric": "MLUPS at phi=0.40 (plain FP32 vs BF16-PDF / learned forcing) at stated slip error",
         "value": round(mlups, 1),
@@ -150,13 +165,12 @@ def run(args):
                    "points_per_particle": (parts or {}).get("n_markers", 0),
                    "mdf_iters": p["mdf_iters"], "storage": p["storage"], "tau": p["tau"],
                    "parallelism": "1 GPU"},
-        "slip_rms": slip,
+        "slip_rms": slip["slip_rms"],
+        "slip": slip,
         "roofline": roof,
         "roofline_collide_stream": roof_collide,
         "kernel_ms_per_step": {g: round(v, 5) for g, v in per_group.items()},
     }
-    del sim
-    torch.cuda.empty_cache()
     if not args.no_forms:
         out["forms"] = run_forms(args)
     if not args.no_cpu:
@@ -164,8 +178,34 @@ def run(args):
     return out
 
 
+def slip_run(binding, w, steps, params=None, mlp=None):
+    """The slip error as the survey's measurement section defines it: the rms of
+    |U_b - D_I u| over the points after the step's final forcing pass, averaged over the
+    last half of a run of `steps` steps from the workload's initial state."""
+    import numpy as np
+
+    p = dict(params if params is not None else w["params"])
+    p["stats_every"] = 0
+    parts = w["particles"]
+    sim = _sim(binding, p, parts)
+    if mlp is not None:
+        sim.set_mlp(*mlp)
+    first = steps // 2
+    sim.step(first)
+    sim.set_stats_every(1)
+    vals = []
+    for _ in range(steps - first):
+        sim.step(1)
+        vals.append(sim.stats()["slip_rms"])
+    fb = sim.stats()["fallbacks"]
+    del sim
+    vals = np.array(vals)
+    return {"slip_rms": float(vals.mean()), "slip_rms_last": float(vals[-1]),
+            "steps": steps, "averaged_steps": int(len(vals)), "fallbacks": int(fb)}
+
+
 def _timed(sim, N, steps, warmup):
-    """MLUPS over `steps` after `warmup`, then the slip rms of one more step"""
+    """MLUPS over `steps` after `warmup` (no slip statistic inside the timed steps)"""
     import torch
 
     sim.set_stats_every(0)
@@ -175,11 +215,8 @@ def _timed(sim, N, steps, warmup):
     sim.step(steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    sim.set_stats_every(1)
-    sim.step(1)
-    st = sim.stats()
     return {"value": round(N * steps / (1e6 * secs), 1), "ms_per_step": round(1e3 * secs / steps, 4),
-            "steps": steps, "warmup": warmup, "slip_rms": st["slip_rms"], "fallbacks": st["fallbacks"]}
+            "steps": steps, "warmup": warmup}
 
 
 def _sim(binding, p, parts):
@@ -189,13 +226,29 @@ def _sim(binding, p, parts):
     return sim
 
 
+def _breakdown(sim, steps=10):
+    """kernel-group times per step (every group bracketed by HIP events)"""
+    sim.set_stats_every(0)
+    sim.set_timing(1)
+    sim.reset_stats()
+    sim.step(steps)
+    st = sim.stats()
+    sim.set_timing(0)
+    return {g: round(st["time_ms"][g] / steps, 5) for g in GROUPS if st["launches"][g]}
+
+
 def run_forms(args):
-    """The other forms of the step on their workloads: PDFs stored as BF16 (384^3, 25033
-    spheres, volume fraction 0.40); the single-pass thickened-shell forcing against plain
-    MDF-3 (2048^2, 4096 disks); and learned forcing (256^3, 2347 spheres, 0.30) against
-    plain 5-pass multi-direct forcing on the same workload.  The network is
-    trained here, on the GPU, on (features, converged force) pairs captured from the
-    plain solver."""
+    """The other forms of the step on their workloads:
+    - PDFs stored as BF16 (384^3, 25033 spheres, volume fraction 0.40);
+    - the paper's single-pass thickened-shell forcing against plain MDF-3 (2048^2, 4096
+      disks);
+    - learned forcing (256^3, 2347 spheres, 0.30) against plain MDF-5 and against MDF-2,
+      the plain method with the same number of spreading passes.  The network is trained
+      here, on the GPU, on (features, converged MDF-5 force) pairs captured from plain runs
+      of a different workload (cavity256_train: 1565 spheres, 0.20, its own seed), so the
+      evaluation set is held out.
+    Each form reports MLUPS over timed steps and the slip averaged over the last half of
+    a run of the workload's length."""
     import numpy as np
     import torch
 
@@ -203,82 +256,99 @@ def run_forms(args):
 
     forms = {}
     steps, warmup = args.form_steps, 3
-    try:
-        w = inputs.workload("cavity384_bf16")
-        p = dict(w["params"])
+
+    def measure(w, name, params=None, mlp=None):
+        p = dict(params if params is not None else w["params"])
         sim = _sim(binding, p, w["particles"])
+        if mlp is not None:
+            sim.set_mlp(*mlp)
         r = _timed(sim, int(np.prod(p["n"])), steps, warmup)
-        r.update({"workload": "cavity384_bf16", "dtype": "bf16-storage/f32",
-                  "particles": len(w["particles"]["center"])})
-        forms["bf16_storage"] = r
+        r["kernel_ms_per_step"] = _breakdown(sim)
+        np_, nmk = sim.counts()
         del sim
         torch.cuda.empty_cache()
+        r["slip"] = slip_run(binding, w, int(w.get("steps", 200)), params=p, mlp=mlp)
+        r["slip_rms"] = r["slip"]["slip_rms"]
+        r.update({"workload": name, "particles": np_, "points": nmk})
+        return r
+
+    try:
+        w = inputs.workload("cavity384_bf16")
+        r = measure(w, "cavity384_bf16")
+        r["dtype"] = "bf16-storage/f32"
+        forms["bf16_storage"] = r
     except Exception as e:  # reported, not fatal for the headline line
         forms["bf16_storage"] = {"error": repr(e)}
     # the paper's own coupling for its particle-laden runs: one forcing pass with the
     # shell thickened to drs = 1.9 (3-point kernel), against plain MDF-3 with the 4-point
     # kernel, on the same lattice and particles (the sparse 2-D layout: at the dense
-    # workloads' packing the single thickened pass does not settle stably)
-    for base_name, st in (("cavity2048_sparse", max(steps, 100)),):
-        key = "btdf_single_pass"
-        try:
-            res = {}
-            for name in (base_name, base_name + "_btdf"):
-                w = inputs.workload(name)
-                p = dict(w["params"])
-                sim = _sim(binding, p, w["particles"])
-                res[name] = _timed(sim, int(np.prod(p["n"])), st, warmup)
-                res[name].update({"delta": ["peskin4", "roma3"][p["delta"]], "drs": p["drs"],
-                                  "mdf_iters": p["mdf_iters"]})
-                del sim
-                torch.cuda.empty_cache()
-            r = dict(res[base_name + "_btdf"])
-            r.update({"workload": base_name + "_btdf", "dtype": "f32", "plain_mdf3": res[base_name]})
-            forms[key] = r
-        except Exception as e:
-            forms[key] = {"error": repr(e)}
+    # workloads' near contacts the single thickened pass does not settle stably)
     try:
-        w = inputs.workload("cavity256_learned")
-        parts = w["particles"]
-        N = int(np.prod(w["params"]["n"]))
-        base = dict(w["params"])
-        plain = dict(base, forcing=0)
-        # training data: features and converged MDF-5 forces of two plain steps
-        sim = _sim(binding, plain, parts)
-        sim.step(warmup)
-        feats, tgts = [], []
-        for _ in range(2):
-            f, t = sim.capture_samples()
-            feats.append(f)
-            tgts.append(t)
-            sim.step(1)
-        del sim
-        f = np.concatenate(feats)
-        t = np.concatenate(tgts)
-        norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
-        xn = (f - norm[:10]) / norm[10:20]
-        tn = (t - norm[20:23]) / norm[23:26]
-        P0 = np.random.default_rng(1).normal(0, 0.1, binding.NPARAM)
-        t0 = time.perf_counter()
-        P, curve = binding.nn_train(xn, tn, P0, epochs=3, batch=8192, lr=2e-3, seed=1)
-        train_s = time.perf_counter() - t0
-        sim = _sim(binding, plain, parts)
-        rp = _timed(sim, N, steps, warmup)
-        del sim
-        sim = _sim(binding, base, parts)
-        sim.set_mlp(P, norm)
-        rl = _timed(sim, N, steps, warmup)
-        del sim
-        torch.cuda.empty_cache()
-        rl.update({"workload": "cavity256_learned", "dtype": "f32, MLP in bf16 on MFMA",
-                   "particles": len(parts["center"]), "correction_passes": 1,
-                   "train": {"samples": int(len(f)), "epochs": 3, "seconds": round(train_s, 2),
-                             "loss_first": float(curve[0]), "loss_last": float(curve[-1])},
-                   "plain_mdf5": rp})
-        forms["learned_forcing"] = rl
+        res = {}
+        for name in ("cavity2048_sparse", "cavity2048_sparse_btdf"):
+            w = inputs.workload(name)
+            p = w["params"]
+            res[name] = measure(w, name)
+            res[name].update({"delta": ["peskin4", "roma3"][p["delta"]], "drs": p["drs"],
+                              "mdf_iters": p["mdf_iters"], "dtype": "f32"})
+        r = dict(res["cavity2048_sparse_btdf"])
+        r["plain_mdf3"] = res["cavity2048_sparse"]
+        forms["btdf_single_pass"] = r
+    except Exception as e:
+        forms["btdf_single_pass"] = {"error": repr(e)}
+    try:
+        forms["learned_forcing"] = learned_form(binding, inputs, measure, warmup)
     except Exception as e:
         forms["learned_forcing"] = {"error": repr(e)}
     return forms
+
+
+def learned_form(binding, inputs, measure, warmup):
+    """Train on captures of the plain cavity256_train runs (held out), evaluate on
+    cavity256_learned: learned + 1 correction pass, plain MDF-5 and plain MDF-2."""
+    import numpy as np
+
+    wt = inputs.workload("cavity256_train")
+    sim = _sim(binding, wt["params"], wt["particles"])
+    sim.step(10)
+    feats, tgts = [], []
+    while sum(len(f) for f in feats) < 4_000_000:
+        f, t = sim.capture_samples()
+        feats.append(f)
+        tgts.append(t)
+        sim.step(5)
+    del sim
+    f = np.concatenate(feats)
+    t = np.concatenate(tgts)
+    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    xn = (f - norm[:10]) / norm[10:20]
+    tn = (t - norm[20:23]) / norm[23:26]
+    P0 = np.random.default_rng(1).normal(0, 0.1, binding.NPARAM)
+    epochs = 4
+    t0 = time.perf_counter()
+    P, curve = binding.nn_train(xn, tn, P0, epochs=epochs, batch=8192, lr=2e-3, seed=1)
+    train_s = time.perf_counter() - t0
+    w = inputs.workload("cavity256_learned")
+    base = dict(w["params"])
+    rl = measure(w, "cavity256_learned", params=base, mlp=(P, norm))
+    rp5 = measure(w, "cavity256_learned", params=dict(base, forcing=0, mdf_iters=5))
+    rp2 = measure(w, "cavity256_learned", params=dict(base, forcing=0, mdf_iters=2))
+    # the MLP kernels (features + BF16 MFMA inference) against the dense BF16 peak
+    t_mlp = rl["kernel_ms_per_step"].get("mlp")
+    if t_mlp:
+        flops = rl["points"] * MLP_FLOP_PER_POINT
+        rl["mlp_mfma"] = {"kernels": "k_features + k_mlp_infer", "ms_per_step": t_mlp,
+                          "flop_per_step": flops,
+                          "achieved_tflops": round(flops / (t_mlp * 1e-3) / 1e12, 3),
+                          "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+                          "frac": round(flops / (t_mlp * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 6)}
+    rl.update({"dtype": "f32, MLP in bf16 on MFMA", "correction_passes": 1,
+               "train": {"workload": "cavity256_train", "samples": int(len(f)),
+                         "captures": len(feats), "epochs": epochs,
+                         "seconds": round(train_s, 2), "loss_first": float(curve[0]),
+                         "loss_last": float(curve[-1])},
+               "plain_mdf5": rp5, "plain_mdf2": rp2})
+    return rl
 
 
 SWEEP = {2: [40, 100, 200, 400, 1000, 2000, 4000, 8192], 3: [40, 80, 128, 160, 210, 256, 384, 480]}
@@ -357,34 +427,76 @@ def run_np_sweep(args, kind="np"):
     return {"sweep": f"{what}, FP32, MDF-3", "unit": "MLUPS", "rows": rows}
 
 
+CPU_CHILD = r"""
+import json, os, sys, time
+sys.path.insert(0, ROOT)
+if PIN is not None:
+    os.sched_setaffinity(0, {PIN})
+import numpy as np
+import oracle
+from paper_2002_08855_amd import inputs
+w = inputs.workload(WORKLOAD)
+p, parts = w["params"], w["particles"]
+s = oracle.Sim(p)
+if parts is not None:
+    s.add_particles(parts["center"], parts["diameter"], parts["density"], n_markers=parts["n_markers"])
+s.step(1)  # warm
+steps, t = 0, 0.0
+while t < BUDGET and steps < 1000:
+    t0 = time.perf_counter()
+    s.step(1)
+    t += time.perf_counter() - t0
+    steps += 1
+print(json.dumps({"steps": steps, "seconds": t, "N": int(np.prod(p["n"]))}))
+"""
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_leg(workload, threads, pin, budget):
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    code = (f"ROOT = {ROOT!r}\nWORKLOAD = {workload!r}\nBUDGET = {budget!r}\nPIN = {pin!r}\n"
+            + CPU_CHILD)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return d
+
+
 def cpu_baseline(w, args):
     """The CPU oracle (FP64, OpenMP over lattice loops) on a bounded sample of the same
-    workload: the same lattice and particles, a few steps."""
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    import numpy as np
-
+    workload (the same lattice and particles, the steps that fit the time budget after one
+    warm-up step), in two child processes: all the host cores this process may use (at
+    most 16), and one thread pinned to one core (the paper's setting is one core)."""
     import oracle
 
-    p = w["params"]
-    parts = w["particles"]
-    s = oracle.Sim(p)
-    if parts is not None:
-        s.add_particles(parts["center"], parts["diameter"], parts["density"],
-                        n_markers=parts["n_markers"])
-    N = int(np.prod(p["n"]))
-    s.step(1)  # warm
-    steps, t = 0, 0.0
-    budget = args.cpu_seconds
-    while t < budget and steps < 1000:
-        t0 = time.perf_counter()
-        s.step(1)
-        t += time.perf_counter() - t0
-        steps += 1
-    return {"value": round(N * steps / (1e6 * t), 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} steps of {args.workload} after 1 warm-up step ({t:.1f} s), "
-                      f"FP64 oracle, OMP_NUM_THREADS={threads}"}
+    allowed = sorted(os.sched_getaffinity(0))
+    threads = min(16, len(allowed))
+    legs = {}
+    for key, nthr, pin in (("all_cores", threads, None), ("single_core", 1, allowed[0])):
+        d = _cpu_leg(args.workload, nthr, pin, args.cpu_seconds)
+        legs[key] = {"value": round(d["N"] * d["steps"] / (1e6 * d["seconds"]), 3),
+                     "unit": "MLUPS", "cores": nthr,
+                     "sample": f"{d['steps']} steps of {args.workload} after 1 warm-up step "
+                               f"({d['seconds']:.1f} s), FP64 oracle, OMP_NUM_THREADS={nthr}"
+                               + (f", pinned to CPU {pin}" if pin is not None else "")}
+    out = dict(legs["all_cores"])
+    out.update({"kind": "oracle", "single_core": legs["single_core"], "cpu_model": _cpu_model(),
+                "host_cpus_allowed": len(allowed),
+                "compiler": f"{oracle.compiler_version()} {' '.join(oracle.CFLAGS)}"})
+    return out
 
 
 def main():

@@ -19,11 +19,19 @@ LIB_PATH = os.path.join(HERE, "libiblbm_ref.so")
 NPARAM = 10 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 
 
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def compiler_version() -> str:
+    r = subprocess.run(["gcc", "--version"], capture_output=True, text=True)
+    return r.stdout.splitlines()[0] if r.returncode == 0 and r.stdout else "gcc"
+
+
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (always recompiles)."""
     src = os.path.join(HERE, "iblbm_ref.c")
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-fopenmp", "-Wall", "-Wno-unknown-pragmas", src, "-o", LIB_PATH + ".tmp", "-lm"]
+    cmd = ["gcc", *CFLAGS, src, "-o", LIB_PATH + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

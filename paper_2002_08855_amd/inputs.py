@@ -92,6 +92,9 @@ def workload(name: str) -> dict:
                         ratio 2.0, BF16/FP16 PDF storage, 200 steps (FCC + deletion).
     cavity256_learned : 3-D 256^3, volume fraction 0.30: 2347 spheres D=16, learned
                         forcing, 200 steps (FCC + deletion).
+    cavity256_train   : the training source of the learned forcing: cavity256_f32's shape
+                        (1565 spheres, 0.20, random sequential addition) with seed 103,
+                        plain MDF-5.
     np2d_<Np> / np3d_<Np>: the particle-count series of Table 7: 2048^2 FP32 with Np
                         disks D=16 (Np <= 10^4), 150^3 FP32 with Np spheres D=12 (Np <= 600),
                         round(pi D) / round(pi D^2) points, ratio 1.5, MDF-3, on a thinned
@@ -198,6 +201,15 @@ def workload(name: str) -> dict:
                      jitter=0.2)
         parts = dict(center=X, diameter=np.full(len(X), 12.0), density=np.full(len(X), 2.0),
                      n_markers=452)
+        return dict(params=p, particles=parts, steps=200)
+    if name == "cavity256_train":
+        # the training runs of the learned forcing: the 256^3 plain workload's shape (volume
+        # fraction 0.20, random sequential addition) with its own seed, plain MDF-5
+        p = default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=5)
+        X = rsa(seed=103, dim=3, n=(256, 256, 256), count=1565, diameter=16.0, gap=0.5,
+                clearance=2.5)
+        parts = dict(center=X, diameter=np.full(len(X), 16.0), density=np.full(len(X), 2.0),
+                     n_markers=804)
         return dict(params=p, particles=parts, steps=200)
     if name == "cavity256_learned":
         p = default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=5, forcing=1)

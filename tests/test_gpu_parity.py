@@ -195,6 +195,30 @@ def test_pairs_cells_bit_exact(dim, n, count):
     assert np.array_equal(g.pairs(), o.pairs())
 
 
+@pytest.mark.parametrize("dim,n,count,band", [(2, (150, 130), 70, None), (2, (150, 130), 70, 1),
+                                            (3, (56, 52, 48), 40, None), (3, (56, 52, 48), 40, 0)])
+def test_dense_shared_support_nodes_f64(dim, n, count, band):
+    """Particles 0.05 to 1.3 lu apart, so that the delta-function supports of neighbours
+    share nodes (two or three particles per node): the force at a shared node is the sum
+    of every particle's spread there, and each particle interpolates it.  MDF-3, FP64,
+    fields and particle states after 24 steps within the FP64 bar."""
+    X, D = _dense_set(dim, n, count, 8.0, 11 + dim, gap_lo=0.05, gap_hi=1.3)
+    p = inputs.default_params(dim, n, tau=0.8, storage="f64", mdf_iters=3)
+    g, o = _pair(p)
+    if band is not None:
+        g.set_band_pass(band)
+    for s in (g, o):
+        s.add_particles(X, D, np.full(len(D), 1.7), n_markers=26 if dim == 2 else 200)
+    assert len(o.pairs()) > count // 2
+    g.step(24)
+    o.step(24)
+    _compare_fields(g, o, 1e-12, f"dense shared {dim}D band={band}")
+    pg, po = g.particles(), o.particles()
+    for k in ("X", "U", "F_h"):
+        assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))
+    assert np.array_equal(g.pairs(), o.pairs())
+
+
 @pytest.mark.parametrize("lds,storage,tol,band,btdf", [
     (1, "f32", 1e-5, None, False), (1, "f32", 1e-5, 0, False), (0, "f32", 1e-5, None, False),
     (1, "f64", 1e-12, None, False), (1, "f64", 1e-12, 0, False),
