@@ -198,10 +198,12 @@ def slip_run(binding, w, steps, params=None, mlp=None):
         sim.step(1)
         vals.append(sim.stats()["slip_rms"])
     fb = sim.stats()["fallbacks"]
+    umax = float(np.abs(sim.particles()["U"]).max())
     del sim
     vals = np.array(vals)
     return {"slip_rms": float(vals.mean()), "slip_rms_last": float(vals[-1]),
-            "steps": steps, "averaged_steps": int(len(vals)), "fallbacks": int(fb)}
+            "steps": steps, "averaged_steps": int(len(vals)), "fallbacks": int(fb),
+            "max_abs_U_end": umax}
 
 
 def _timed(sim, N, steps, warmup):
@@ -387,7 +389,7 @@ NP_SWEEP = {2: [1, 10, 100, 1000, 5000, 10000], 3: [1, 10, 100, 300, 600]}
 RES_SWEEP = {2: [12, 16, 24, 32, 40, 48], 3: [12, 16, 20, 24, 30]}
 
 
-def run_np_sweep(args, kind="np"):
+def run_np_sweep(args, kind="np", suffix=""):
     """The particle-count series of Table 7 (Sec. 6.2.1; kind "np": 2048^2 with D = 16,
     150^3 with D = 12) or the resolution series of Sec. 6.2.2 (kind "res": a 40 D square
     with 400 disks, a 5 D cube with 27 spheres): whole-step MLUPS and the time of each
@@ -401,7 +403,7 @@ def run_np_sweep(args, kind="np"):
     series = NP_SWEEP if kind == "np" else RES_SWEEP
     for dim in (2, 3):
         for v in series[dim]:
-            w = inputs.workload(f"{kind}{dim}d_{v}")
+            w = inputs.workload(f"{kind}{dim}d_{v}{suffix}")
             p, parts = w["params"], w["particles"]
             N = int(np.prod(p["n"]))
             sim = _sim(binding, p, parts)
@@ -415,16 +417,22 @@ def run_np_sweep(args, kind="np"):
             sim.set_timing(0)
             groups = {g: round(st["time_ms"][g] / 20, 5) for g in GROUPS if st["launches"][g]}
             np_, nmk = sim.counts()
-            rows.append({"dim": dim, "n": list(p["n"][:dim]), "diameter": float(parts["diameter"][0]),
-                         "particles": np_, "points": nmk,
-                         "mesh_ratio": round(nmk / N, 6), "mlups": r["value"],
-                         "ms_per_step": r["ms_per_step"], "slip_rms": r["slip_rms"],
-                         "kernel_ms_per_step": groups})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
             del sim
             torch.cuda.empty_cache()
+            # the paper's run length (1000 steps in 2-D, 200 in 3-D), from rest: slip over
+            # its last half, and the largest particle speed at its end
+            slip = slip_run(binding, w, int(w.get("steps", 200)))
+            rows.append({"dim": dim, "n": list(p["n"][:dim]), "diameter": float(parts["diameter"][0]),
+                         "particles": np_, "points": nmk, "density_ratio": float(parts["density"][0]),
+                         "mesh_ratio": round(nmk / N, 6), "mlups": r["value"],
+                         "ms_per_step": r["ms_per_step"], "slip_rms": slip["slip_rms"],
+                         "run_steps": slip["steps"], "max_abs_U_end": slip["max_abs_U_end"],
+                         "kernel_ms_per_step": groups})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     what = "particle count (Table 7)" if kind == "np" else "particle resolution (Sec. 6.2.2)"
-    return {"sweep": f"{what}, FP32, MDF-3", "unit": "MLUPS", "rows": rows}
+    how = ("3-point kernel, drs 1.9, one forcing pass, density ratio 1.01 (Sec. 6.2)"
+           if suffix else "MDF-3, 4-point kernel, density ratio 1.5")
+    return {"sweep": f"{what}, FP32, {how}", "unit": "MLUPS", "rows": rows}
 
 
 CPU_CHILD = r"""
@@ -516,6 +524,9 @@ def main():
     ap.add_argument("--np-sweep", action="store_true",
                     help="instead of the headline line: MLUPS and kernel-group times against "
                          "the number of particles (Table 7)")
+    ap.add_argument("--np-sweep-paper", action="store_true",
+                    help="the particle-count series in the paper's setting (3-point kernel, "
+                         "drs 1.9, one forcing pass, density ratio 1.01)")
     ap.add_argument("--res-sweep", action="store_true",
                     help="instead of the headline line: the same against the particle "
                          "resolution (Sec. 6.2.2)")
@@ -529,6 +540,9 @@ def main():
         return
     if args.np_sweep:
         print(json.dumps(run_np_sweep(args)), flush=True)
+        return
+    if args.np_sweep_paper:
+        print(json.dumps(run_np_sweep(args, suffix="_paper")), flush=True)
         return
     if args.res_sweep:
         print(json.dumps(run_np_sweep(args, "res")), flush=True)

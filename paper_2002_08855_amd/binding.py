@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -174,12 +175,19 @@ def make_config(p: dict, stream=None, use_torch_alloc=True):
         import torch
 
         dev = torch.cuda.current_device()
+        alloc_fn = torch.cuda.caching_allocator_alloc
+        free_fn = torch.cuda.caching_allocator_delete
+        finalizing = sys.is_finalizing
 
         def _alloc(nbytes, user):
-            return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+            return alloc_fn(int(nbytes), dev)
 
         def _free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            # A context still alive at interpreter exit is destroyed after torch's
+            # modules are torn down; the process is ending and the driver reclaims
+            # its memory, so the block is left to it.
+            if not finalizing():
+                free_fn(ptr)
 
         fa, ff = _ALLOC(_alloc), _FREE(_free)
         c.dev_alloc = fa

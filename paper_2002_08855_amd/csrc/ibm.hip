@@ -318,6 +318,8 @@ __device__ __forceinline__ void unit_of(const LdsArgs<C>& a, int q, int& p, int&
 // List entries a lane loads before it uses any of them, so that their global-memory
 // latencies overlap.
 constexpr int LIST_BATCH = 4;
+// nodes whose PDFs a lane of the first interpolation pass loads before it uses any
+constexpr int FIRST_BATCH = 3;
 
 // LDS layout of the per-particle interpolation kernel (the host sizes the dynamic LDS
 // with the same function): C ub[DIM][cap] staged velocities, uint8 flag[cap] touched
@@ -511,22 +513,34 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   T* slot[L::Q - 1];
   if (FIRST) slots_of<DIM, T>(a.slot, slot);
   if (FIRST) {
-    // u* from the PDFs at the listed nodes (Eqs. 4-5); the force there starts at zero
-    for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
-      const int t = nodes[j];
-      int x, y, z;
-      b.at(t, x, y, z);
-      const int ii = x + a.g.n[0] * (y + a.g.n[1] * z);
-      const size_t i = (size_t)ii * a.vd;
-      C f[L::Q];
-      load_all<DIM, T, PAR>(slot, a.geo, x, y, z, ii, a.inv_s, f);
-      C S, u[3];
-      moments<DIM, C>(f, a.geo.rho0, S, u);
+    // u* from the PDFs at the listed nodes (Eqs. 4-5); the force there starts at zero.
+    // FIRST_BATCH nodes per lane at a time, their PDF loads issued before any is used, so
+    // that the loads of several nodes share one memory latency
+    for (int j0 = threadIdx.x; j0 < ntouch; j0 += FIRST_BATCH * blockDim.x) {
+      int t[FIRST_BATCH], ii[FIRST_BATCH];
+      C f[FIRST_BATCH][L::Q];
 #pragma unroll
-      for (int c = 0; c < DIM; c++) ub[c * a.cap + t] = u[c];
-      store_node<DIM>(a.ustar, i, u);
-      const C zero[3] = {C(0), C(0), C(0)};
-      store_node<DIM>(a.facc, i, zero);
+      for (int v = 0; v < FIRST_BATCH; v++) {
+        const int j = j0 + v * (int)blockDim.x;
+        t[v] = j < ntouch ? (int)nodes[j] : -1;
+        if (t[v] < 0) continue;
+        int x, y, z;
+        b.at(t[v], x, y, z);
+        ii[v] = x + a.g.n[0] * (y + a.g.n[1] * z);
+        load_all<DIM, T, PAR>(slot, a.geo, x, y, z, ii[v], a.inv_s, f[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < FIRST_BATCH; v++) {
+        if (t[v] < 0) continue;
+        const size_t i = (size_t)ii[v] * a.vd;
+        C S, u[3];
+        moments<DIM, C>(f[v], a.geo.rho0, S, u);
+#pragma unroll
+        for (int c = 0; c < DIM; c++) ub[c * a.cap + t[v]] = u[c];
+        store_node<DIM>(a.ustar, i, u);
+        const C zero[3] = {C(0), C(0), C(0)};
+        store_node<DIM>(a.facc, i, zero);
+      }
     }
   } else {
     // u* + F / (2 rho0) at the listed nodes, LIST_BATCH entries per lane at a time

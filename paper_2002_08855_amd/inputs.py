@@ -99,6 +99,9 @@ def workload(name: str) -> dict:
                         disks D=16 (Np <= 10^4), 150^3 FP32 with Np spheres D=12 (Np <= 600),
                         round(pi D) / round(pi D^2) points, ratio 1.5, MDF-3, on a thinned
                         square or cubic lattice (pitch 20 / 15, jitter 1).
+    np2d_<Np>_paper / np3d_<Np>_paper: the same series in the paper's setting of Sec. 6.2:
+                        3-point kernel, drs = 1.9, one forcing pass, density ratio 1.01
+                        (3-D jitter 0.5, so that surface gaps stay at 2 lu or more).
     res2d_<D> / res3d_<D>: the resolution series of Sec. 6.2.2: a 40 D square with 400
                         disks (20 x 20 grid, pitch 2 D) / a 5 D cube with 27 spheres (pitch
                         5 D / 3), diameter D, FP32, ratio 1.5, MDF-3.
@@ -113,8 +116,12 @@ def workload(name: str) -> dict:
     """
     if name.startswith("np2d_") or name.startswith("np3d_"):
         # the particle-count series of Table 7 (Sec. 6.2.1): 2048^2 with D = 16 up to 10^4
-        # disks, 150^3 with D = 12 up to 600 spheres; plain MDF-3, density ratio 1.5
+        # disks, 150^3 with D = 12 up to 600 spheres; plain MDF-3, density ratio 1.5.
+        # With the suffix _paper: the paper's own setting of Sec. 6.2 (the 3-point kernel,
+        # a shell of drs = 1.9, one forcing pass, density ratio 1.01), on lattices whose
+        # surface gaps stay at 2 lu or more (3-D jitter 0.5)
         dim = 2 if name.startswith("np2d_") else 3
+        paper = name.endswith("_paper")
         count = int(name.split("_")[1])
         if dim == 2:
             p = default_params(2, (2048, 2048), tau=0.6, storage="f32", mdf_iters=3)
@@ -124,11 +131,15 @@ def workload(name: str) -> dict:
         else:
             p = default_params(3, (150, 150, 150), tau=0.7, storage="f32", mdf_iters=3)
             X = lattice_pick(seed=8, dim=3, n=(150, 150, 150), count=count, diameter=12.0,
-                             pitch=15.0, clearance=2.5, jitter=1.0)
+                             pitch=15.0, clearance=2.5, jitter=0.5 if paper else 1.0)
             D = 12.0
-        parts = dict(center=X, diameter=np.full(count, D), density=np.full(count, 1.5),
+        rho = 1.5
+        if paper:
+            p.update(delta=1, drs=1.9, mdf_iters=1)
+            rho = 1.01
+        parts = dict(center=X, diameter=np.full(count, D), density=np.full(count, rho),
                      n_markers=0)
-        return dict(params=p, particles=parts, steps=200)
+        return dict(params=p, particles=parts, steps=1000 if dim == 2 else 200)
     if name.startswith("res2d_") or name.startswith("res3d_"):
         # the resolution series of Sec. 6.2.2: a 40 D square / 5 D cube with the particle
         # diameter D in lattice units; the number of particles (400 / 27) and so the

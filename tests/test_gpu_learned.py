@@ -170,12 +170,20 @@ def _norm_stats(f, t):
 
 
 def test_learned_forcing_gain_over_mdf():
-    """Train on (features, converged MDF-5 force) pairs from plain runs, then compare the
-    slip after the learned force + one correction pass with MDF-2 (the same number of
-    spreading passes) and MDF-5, from the same state."""
-    X, D, rho = _cavity(seed=23)
+    """Train on (features, converged MDF-5 force) pairs from plain runs of two layouts,
+    then, on a third layout held out of training, compare the slip after the learned
+    force + one correction pass with MDF-2 (the same number of spreading passes) and
+    MDF-5, from the same state."""
     base = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f32", mdf_iters=5)
-    f, t = _collect(base, X, D, rho, 40)
+    # trained on two layouts, evaluated on a third that it never saw
+    fs, ts = [], []
+    for seed in (41, 42):
+        Xt, Dt, rhot = _cavity(seed=seed)
+        f, t = _collect(base, Xt, Dt, rhot, 20)
+        fs.append(f)
+        ts.append(t)
+    f, t = np.concatenate(fs), np.concatenate(ts)
+    X, D, rho = _cavity(seed=23)
     norm = _norm_stats(f, t)
     xn = (f - norm[:10]) / norm[10:20]
     tn = (t - norm[20:23]) / norm[23:26]
@@ -205,26 +213,53 @@ def test_learned_forcing_gain_over_mdf():
 
 
 def test_learned_step_matches_oracle():
-    """The learned step (same trained-like weights on both sides, BF16 MFMA on the GPU)
-    agrees with the FP64 oracle within the BF16 rounding of the prediction."""
+    """The learned step with an MLP whose outputs are O(1) and whose output scale is the
+    converged MDF-5 force of this layout, so that the prediction carries the whole
+    boundary force before the correction pass: GPU (BF16 MFMA, FP32 accumulation)
+    against the FP64 oracle on the same BF16-rounded weights, 5 steps.
+
+    Bound: BF16 keeps 8 significant bits (unit roundoff u = 2^-9).  The inputs, the
+    weights and both hidden activations are rounded, four stages of at most 2u each on
+    the prediction, so 8u = 2^-6 relative; the step's force is the prediction plus one
+    correction pass, which removes part of that error, and the fields follow the force.
+    The MLP's share of the step is checked to be far above the bound: the oracle's step
+    with the prediction replaced by its mean differs by more than ten times the measured
+    GPU error."""
     X, D, rho = _cavity(seed=25)
-    p = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f64", mdf_iters=5, forcing=1,
-                              slip_tol=1e30)
-    g, o = _sim_pair(p, X, D, rho)
-    P = _bf16(_params(11, 0.05))
-    norm = np.concatenate([np.zeros(10), np.full(10, 1e-4), np.zeros(3), np.full(3, 1e-4)])
-    norm[16:19] = 1.0  # normals are O(1)
-    norm[19] = 1.0
-    g.set_mlp(P, norm)
-    o.set_mlp(P, norm)
+    p = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f64", mdf_iters=5)
+    o0 = oracle.Sim(p)
+    o0.add_particles(X, D, rho, n_markers=452)
+    o0.step(5)
+    f, t = o0.capture_samples()
+    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    P = _bf16(_params(11, 0.3))
+    y = oracle.mlp_forward(P, (f - norm[:10]) / norm[10:20])
+    print("MLP output std per component", y.std(0))
+    assert np.all(y.std(0) > 0.3) and np.abs(y).max() < 10
+    pl = dict(p, forcing=1, slip_tol=1e30)
+    g, o = _sim_pair(pl, X, D, rho)
     for s in (g, o):
+        s.set_mlp(P, norm)
         s.step(5)
     pg, ug, fg = g.fields()
     po, uo, fo = o.fields()
-    eu = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
-    ef = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
-    print("learned step rel-L2 u, force", eu, ef)
-    assert eu < 2e-2 and ef < 2e-2
+    err = {"u": np.linalg.norm(ug - uo) / np.linalg.norm(uo),
+           "force": np.linalg.norm(fg - fo) / np.linalg.norm(fo),
+           "U": np.linalg.norm(g.particles()["U"] - o.particles()["U"]) / np.linalg.norm(
+               o.particles()["U"])}
+    mean_only = norm.copy()
+    mean_only[23:26] = 0.0
+    om = oracle.Sim(pl)
+    om.add_particles(X, D, rho, n_markers=452)
+    om.set_mlp(P, mean_only)
+    om.step(5)
+    _, um, fm = om.fields()
+    share = min(np.linalg.norm(um - uo) / np.linalg.norm(uo),
+                np.linalg.norm(fm - fo) / np.linalg.norm(fo))
+    print("learned step rel-L2", err, "MLP share", share)
+    for k, v in err.items():
+        assert v < 2.0 ** -6, (k, v)
+    assert share > 10 * max(err["u"], err["force"])
 
 
 def test_fallback_engages_on_tight_tolerance():

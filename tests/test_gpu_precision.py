@@ -72,10 +72,13 @@ def _run_pair(storage):
     return err
 
 
-# FP32 storage: the error grows with the particle interactions of this dense case to
-# about 2e-5 after 100 steps (the same with float-atomic spreading, so it is the FP32
-# arithmetic itself); the 1e-5 parity bar of the FP32 mode is checked on the parity
-# cases and on the full 2048^2 workload over 100 steps.
+# FP32 storage at this density (0.37, 108 spheres within 1 lu of each other): the error
+# grows with the particle interactions to about 2e-5 after 100 steps.  Rounding every
+# stored PDF, u*, IB field and point force of the FP64 oracle to FP32 moves u by only
+# 1e-7 over the same run, and the per-particle LDS and point-wise spreading paths give
+# the same figure, so the growth comes from FP32 arithmetic inside the step amplified
+# by the near-contact pairs, not from storage or summation order.  The 1e-5 bar of the
+# FP32 mode is checked at the 256^3 workload's particle size and fraction below.
 @pytest.mark.parametrize("storage,bound", [("f32", 1e-4), ("f16", 5e-3), ("bf16", 3e-2)])
 def test_storage_error_per_field(storage, bound):
     """64^3 cavity, 108 spheres D=12 (452 points each, density ratio 2), 100 steps,
@@ -89,6 +92,37 @@ def test_storage_error_per_field(storage, bound):
     for k in ("u", "force", "U", "X_disp"):
         assert err[k] < bound, (k, err[k])
     assert abs(err["slip_gpu"] - err["slip_oracle"]) < 0.1 * err["slip_oracle"] + 1e-9
+
+
+def test_f32_parity_at_the_256_cube_particle_size_and_fraction():
+    """FP32 storage against the FP64 oracle: a 96^3 cavity holding 82 spheres of
+    diameter 16 lu (804 points each) placed at random with gaps of at least 0.5 lu,
+    volume fraction 0.20 (the 256^3 workload's), density ratio 2, MDF-3, 100 steps.
+    Every field and the particle velocities within 1e-5 relative L2, and the largest
+    pointwise deviation within 1e-5 of each field's largest magnitude."""
+    b = _gpu()
+    n = (96, 96, 96)
+    X = inputs.rsa(seed=31, dim=3, n=n, count=82, diameter=16.0, gap=0.5, clearance=2.5)
+    D = np.full(len(X), 16.0)
+    rho = np.full(len(X), 2.0)
+    p = inputs.default_params(3, n, tau=0.7, storage="f64", mdf_iters=3)
+    o = oracle.Sim(p)
+    g = b.Sim(dict(p, storage="f32"))
+    for s in (o, g):
+        s.add_particles(X, D, rho, n_markers=804)
+        s.step(100)
+    err = {}
+    for name, a, r in zip(("p", "u", "force"), g.fields(), o.fields()):
+        err[name] = rel_l2(a, r)
+        err[name + "_max"] = float(np.abs(a - r).max() / np.abs(r).max())
+    err["U"] = rel_l2(g.particles()["U"], o.particles()["U"])
+    print("f32 96^3 phi 0.20", json.dumps(err))
+    if OUT:
+        os.makedirs(OUT, exist_ok=True)
+        with open(os.path.join(OUT, "precision_f32_phi020.json"), "w") as fh:
+            json.dump(err, fh)
+    for k, v in err.items():
+        assert v < 1e-5, (k, v)
 
 
 def test_f16_scale_power_of_two_roundtrip():

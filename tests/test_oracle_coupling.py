@@ -63,3 +63,15 @@ def test_paper_settling_setting_3d_stable():
     umax, _ = _settle(3, (48, 48, 48), X, 12.0, 200, 50)
     print("max |U| every 50 steps", umax)
     assert max(umax) < 1e-4
+
+
+def test_paper_settling_setting_3d_dense_stable():
+    """Table 7 3-D towards its dense end: 27 spheres of D = 12 on the cubic lattice of the
+    particle-count series (pitch 15, jitter 0.5, so surface gaps of at least 2 lu) in a
+    60^3 cavity (volume fraction 0.11, between the series' 300 and 600 spheres), the
+    paper's 200 steps, bounded."""
+    X = inputs.lattice_pick(seed=8, dim=3, n=(60, 60, 60), count=27, diameter=12.0, pitch=15.0,
+                            clearance=2.5, jitter=0.5)
+    umax, _ = _settle(3, (60, 60, 60), X, 12.0, 200, 50)
+    print("max |U| every 50 steps", umax)
+    assert max(umax) < 1e-3
