@@ -239,7 +239,7 @@ def _breakdown(sim, steps=10):
     return {g: round(st["time_ms"][g] / steps, 5) for g in GROUPS if st["launches"][g]}
 
 
-def run_forms(args):
+def run_forms(args, only=None):
     """The other forms of the step on their workloads:
     - PDFs stored as BF16 (384^3, 25033 spheres, volume fraction 0.40);
     - the paper's single-pass thickened-shell forcing against plain MDF-3 (2048^2, 4096
@@ -250,7 +250,8 @@ def run_forms(args):
       of a different workload (cavity256_train: 1565 spheres, 0.20, its own seed), so the
       evaluation set is held out.
     Each form reports MLUPS over timed steps and the slip averaged over the last half of
-    a run of the workload's length."""
+    a run of the workload's length.  `only` names one form to run by itself (for a
+    profiler run)."""
     import numpy as np
     import torch
 
@@ -274,18 +275,16 @@ def run_forms(args):
         r.update({"workload": name, "particles": np_, "points": nmk})
         return r
 
-    try:
-        w = inputs.workload("cavity384_bf16")
-        r = measure(w, "cavity384_bf16")
+    def bf16_storage():
+        r = measure(inputs.workload("cavity384_bf16"), "cavity384_bf16")
         r["dtype"] = "bf16-storage/f32"
-        forms["bf16_storage"] = r
-    except Exception as e:  # reported, not fatal for the headline line
-        forms["bf16_storage"] = {"error": repr(e)}
-    # the paper's own coupling for its particle-laden runs: one forcing pass with the
-    # shell thickened to drs = 1.9 (3-point kernel), against plain MDF-3 with the 4-point
-    # kernel, on the same lattice and particles (the sparse 2-D layout: at the dense
-    # workloads' near contacts the single thickened pass does not settle stably)
-    try:
+        return r
+
+    def btdf_single_pass():
+        # the paper's own coupling for its particle-laden runs: one forcing pass with the
+        # shell thickened to drs = 1.9 (3-point kernel), against plain MDF-3 with the
+        # 4-point kernel, on the same lattice and particles (the sparse 2-D layout: at the
+        # dense workloads' near contacts the single thickened pass does not settle stably)
         res = {}
         for name in ("cavity2048_sparse", "cavity2048_sparse_btdf"):
             w = inputs.workload(name)
@@ -295,13 +294,19 @@ def run_forms(args):
                               "mdf_iters": p["mdf_iters"], "dtype": "f32"})
         r = dict(res["cavity2048_sparse_btdf"])
         r["plain_mdf3"] = res["cavity2048_sparse"]
-        forms["btdf_single_pass"] = r
-    except Exception as e:
-        forms["btdf_single_pass"] = {"error": repr(e)}
-    try:
-        forms["learned_forcing"] = learned_form(binding, inputs, measure, warmup)
-    except Exception as e:
-        forms["learned_forcing"] = {"error": repr(e)}
+        return r
+
+    def learned_forcing():
+        return learned_form(binding, inputs, measure, warmup)
+
+    for name, fn in (("bf16_storage", bf16_storage), ("btdf_single_pass", btdf_single_pass),
+                     ("learned_forcing", learned_forcing)):
+        if only not in (None, name):
+            continue
+        try:
+            forms[name] = fn()
+        except Exception as e:  # reported, not fatal for the headline line
+            forms[name] = {"error": repr(e)}
     return forms
 
 
@@ -518,6 +523,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and learned-forcing forms")
     ap.add_argument("--form-steps", type=int, default=20)
+    ap.add_argument("--form", choices=["bf16_storage", "btdf_single_pass", "learned_forcing"],
+                    help="instead of the headline line: run one form by itself")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line: MLUPS of the particle-free channel "
                          "(inflow/outflow faces) against the domain size")
@@ -546,6 +553,9 @@ def main():
         return
     if args.res_sweep:
         print(json.dumps(run_np_sweep(args, "res")), flush=True)
+        return
+    if args.form:
+        print(json.dumps(run_forms(args, only=args.form)), flush=True)
         return
     out = run(args)
     print(json.dumps(out), flush=True)

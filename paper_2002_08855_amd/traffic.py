@@ -34,14 +34,15 @@ COPY_BYTES = 1 << 30
 SOURCE_OF = {"k_collide_stream": "lbm.hip", "k_interior": "lbm.hip", "k_interp_lds": "ibm.hip",
              "k_spread_lds": "ibm.hip", "k_band_prep": "ibm.hip", "k_ustar_all": "lbm.hip",
              "k_mark_lds": "ibm.hip", "k_pairs": "particles.hip",
-             "k_cells": "particles.hip", "k_loads_newton": "particles.hip"}
+             "k_cells": "particles.hip", "k_loads_newton": "particles.hip",
+             "k_features": "mlp.hip", "k_mlp_infer": "mlp.hip"}
 
 
 def source_sha(kernel):
     """hash of the kernel's source file, the headers every kernel includes and the host
     code that sets the launch shapes and work units"""
     h = hashlib.sha256()
-    for f in (SOURCE_OF[kernel], "common.h", "pdf_access.h", "host.hip"):
+    for f in (SOURCE_OF[kernel], "common.h", "pdf_access.h", "index_math.h", "host.hip"):
         h.update(open(os.path.join(ROOT, "paper_2002_08855_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -63,6 +64,13 @@ def run(args):
     if parts is not None:
         sim.add_particles(parts["center"], parts["diameter"], parts["density"],
                           n_markers=parts["n_markers"])
+    if p.get("forcing") == 1:
+        # the learned form: the bytes the MLP kernels move do not depend on the weights
+        import numpy as np
+
+        P = np.random.default_rng(0).normal(0.0, 0.1, binding.NPARAM)
+        norm = np.concatenate([np.zeros(10), np.ones(10), np.zeros(3), np.full(3, 1e-6)])
+        sim.set_mlp(P, norm)
     sim.step(args.steps)
     torch.cuda.synchronize()
     print(json.dumps({"workload": args.workload, "steps": args.steps}), flush=True)
