@@ -1255,6 +1255,8 @@ static void mlp_offsets(const double* P, const double** W1, const double** b1, c
 void ref_mlp_forward(const double* params, int64_t n, const double* x, double* y) {
   const double *W1, *b1, *W2, *b2, *W3, *b3;
   mlp_offsets(params, &W1, &b1, &W2, &b2, &W3, &b3);
+  /* samples are independent: the result does not depend on the thread count */
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < n; s++) {
     double h1[NH], h2[NH];
     for (int o = 0; o < NH; o++) {

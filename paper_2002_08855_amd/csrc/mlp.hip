@@ -2,12 +2,12 @@
 // converged multi-direct-forcing force of every Lagrangian point from its pass-0 slip,
 // its previous-step force, its unit normal and the gap to the nearest other surface.
 //
-// Inference runs on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16) with FP32
-// accumulation.  Each layer is computed transposed, H^T = W X^T: the weights are the A
-// operand and a 16-point tile of activations the B operand, so the D fragment of one
-// layer (lane l: point l%16, units 4*(l/16)..+3 of a 16-unit block) is exactly the B
-// fragment the next layer needs and no data moves between layers.  One wavefront walks
-// 16-point tiles with all weights held in registers.
+// Inference runs on the BF16 matrix cores with FP32 accumulation (v_mfma_f32_16x16x16_bf16
+// for the 10-input layer, v_mfma_f32_16x16x32_bf16 for the two 64-input layers).  Each
+// layer is computed transposed, H^T = W X^T: the weights are the A operand and a 16-point
+// tile of activations the B operand, so the D fragment of one layer is the B fragment the
+// next layer needs and no data moves between layers.  One wavefront walks 16-point tiles
+// with all weights held in registers.
 //
 // Training uses the same library: FP32 GEMMs through LDS tiles, fused elementwise
 // kernels and Adam, all on the GPU.
@@ -26,24 +26,26 @@ void part_zero_cells(iblbm_ctx* c);
 namespace {
 
 constexpr int NI = 10, NH = 64, NO = 3;
+constexpr int INFER_WAVES = 256 * 4 * 3;
 constexpr int NPARAM = NI * NH + NH + NH * NH + NH + NH * NO + NO;
 constexpr int OFF_W1 = 0, OFF_B1 = NI * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NO;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return short((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return short(u >> 16);
+  // round to nearest even (v_cvt_pk_bf16_f32)
+  return __builtin_bit_cast(short, (__bf16)f);
 }
 
+// tanh x = 1 - 2 / (e^{2x} + 1): one exponential and one reciprocal, saturating to +-1
+// without a clamp (e^{2x} overflows to inf or underflows to 0).  Its error, about one
+// FP32 ulp of 1, is far below the BF16 rounding that follows.
 __device__ __forceinline__ float fast_tanh(float x) {
-  x = fminf(fmaxf(x, -15.f), 15.f);
-  float t = __expf(2.f * x);
-  return (t - 1.f) / (t + 1.f);
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 / ln 2
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
 }
 
 struct InferArgs {
@@ -58,14 +60,33 @@ struct InferArgs {
   float* y;  // optional n x 3 raw outputs (normalised units)
 };
 
-// weight fragment of A = W[rb*16 + i][kb*16 + k] for lane l: i = l%16, k = 4(l/16)+v
-__device__ __forceinline__ bf16x4 wfrag(const float* W, int rows, int cols, int rb, int kb, int lane) {
+// Layer 1 (K = 10 inputs, padded to 16) uses v_mfma_f32_16x16x16_bf16: lane l holds
+// A = W[rb*16 + l%16][4(l/16) + v] and B = X[4(l/16) + v][point l%16], v < 4.
+__device__ __forceinline__ bf16x4 wfrag16(const float* W, int rows, int cols, int rb, int lane) {
   bf16x4 a;
-  int i = rb * 16 + (lane & 15), k0 = kb * 16 + 4 * (lane >> 4);
+  const int i = rb * 16 + (lane & 15), k0 = 4 * (lane >> 4);
   for (int v = 0; v < 4; v++) {
-    int k = k0 + v;
+    const int k = k0 + v;
     a[v] = (i < rows && k < cols) ? to_bf16(W[i * cols + k]) : short(0);
   }
+  return a;
+}
+
+// Layers 2 and 3 (K = 64) use v_mfma_f32_16x16x32_bf16, two K blocks of 32.  A layer's
+// D fragment leaves lane l with units 16 rb + 4(l/16) + v (v < 4) of each 16-unit row
+// block rb; the B fragment of K block kb takes, in its 8 slots, those of row blocks 2kb
+// (slots 0-3) and 2kb+1 (slots 4-7).  The contraction runs over whatever order the
+// slots stand for, so the weights are loaded in the same order: slot v of lane l holds
+// unit 32 kb + 16 (v/4) + 4(l/16) + v%4, and no data moves between layers.
+__device__ __forceinline__ int kunit(int kb, int lane, int v) {
+  return 32 * kb + 16 * (v >> 2) + 4 * (lane >> 4) + (v & 3);
+}
+
+__device__ __forceinline__ bf16x8 wfrag32(const float* W, int rows, int cols, int rb, int kb,
+                                          int lane) {
+  bf16x8 a;
+  const int i = rb * 16 + (lane & 15);
+  for (int v = 0; v < 8; v++) a[v] = i < rows ? to_bf16(W[i * cols + kunit(kb, lane, v)]) : short(0);
   return a;
 }
 
@@ -79,50 +100,64 @@ __device__ __forceinline__ floatx4 bfrag(const float* b, int rows, int rb, int l
   return c;
 }
 
+// One wavefront walks 16-point tiles with every weight in registers; the features of
+// the next tile are loaded before the current one is computed.
 __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
-  int lane = threadIdx.x & 63;
-  int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const float* P = a.P;
-  bf16x4 a1[4], a2[4][4], a3[4];
+  bf16x4 a1[4];
+  bf16x8 a2[4][2], a3[2];
   floatx4 c1[4], c2[4], c3;
   for (int rb = 0; rb < 4; rb++) {
-    a1[rb] = wfrag(P + OFF_W1, NH, NI, rb, 0, lane);
+    a1[rb] = wfrag16(P + OFF_W1, NH, NI, rb, lane);
     c1[rb] = bfrag(P + OFF_B1, NH, rb, lane);
     c2[rb] = bfrag(P + OFF_B2, NH, rb, lane);
-    for (int kb = 0; kb < 4; kb++) a2[rb][kb] = wfrag(P + OFF_W2, NH, NH, rb, kb, lane);
-    a3[rb] = wfrag(P + OFF_W3, NO, NH, 0, rb, lane);
+    for (int kb = 0; kb < 2; kb++) a2[rb][kb] = wfrag32(P + OFF_W2, NH, NH, rb, kb, lane);
   }
+  for (int kb = 0; kb < 2; kb++) a3[kb] = wfrag32(P + OFF_W3, NO, NH, 0, kb, lane);
   c3 = bfrag(P + OFF_B3, NO, 0, lane);
-  const float* mean = a.norm;
-  const float* sd = a.norm + NI;
+  // this lane's four input features: mean and reciprocal standard deviation
+  const int j = lane & 15, kq = 4 * (lane >> 4);
+  float mu[4], isd[4];
+  for (int v = 0; v < 4; v++) {
+    const int k = kq + v;
+    mu[v] = k < NI ? a.norm[k] : 0.f;
+    isd[v] = k < NI ? 1.f / a.norm[NI + k] : 0.f;
+  }
   const float* tmean = a.norm + 2 * NI;
   const float* tsd = a.norm + 2 * NI + NO;
-  int j = lane & 15, kq = 4 * (lane >> 4);
-  for (int t0 = wave * 16; t0 < a.n; t0 += nwaves * 16) {
-    int m = t0 + j;
-    bool ok = m < a.n;
-    // B operand of layer 1: features kq..kq+3 of point m, normalised
-    bf16x4 b1;
+  float xin[4];
+  auto load_tile = [&](int t0) {
+    const int m = t0 + j;
     for (int v = 0; v < 4; v++) {
-      int k = kq + v;
-      float x = (ok && k < NI) ? (a.feat[(size_t)m * NI + k] - mean[k]) / sd[k] : 0.f;
-      b1[v] = to_bf16(x);
+      const int k = kq + v;
+      xin[v] = (m < a.n && k < NI) ? a.feat[(size_t)m * NI + k] : 0.f;
     }
-    bf16x4 b2[4], b3[4];
+  };
+  int t0 = wave * 16;
+  if (t0 < a.n) load_tile(t0);
+  for (; t0 < a.n; t0 += nwaves * 16) {
+    const int m = t0 + j;
+    const bool ok = m < a.n;
+    bf16x4 b1;
+    for (int v = 0; v < 4; v++) b1[v] = to_bf16((xin[v] - mu[v]) * isd[v]);
+    if (t0 + nwaves * 16 < a.n) load_tile(t0 + nwaves * 16);
+    bf16x8 b2[2], b3[2];
     for (int rb = 0; rb < 4; rb++) {
-      floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[rb], b1, c1[rb], 0, 0, 0);
-      for (int v = 0; v < 4; v++) b2[rb][v] = to_bf16(fast_tanh(d[v]));
+      const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[rb], b1, c1[rb], 0, 0, 0);
+      for (int v = 0; v < 4; v++) b2[rb >> 1][4 * (rb & 1) + v] = to_bf16(fast_tanh(d[v]));
     }
     for (int rb = 0; rb < 4; rb++) {
       floatx4 d = c2[rb];
-      for (int kb = 0; kb < 4; kb++)
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[rb][kb], b2[kb], d, 0, 0, 0);
-      for (int v = 0; v < 4; v++) b3[rb][v] = to_bf16(fast_tanh(d[v]));
+      for (int kb = 0; kb < 2; kb++)
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[rb][kb], b2[kb], d, 0, 0, 0);
+      for (int v = 0; v < 4; v++) b3[rb >> 1][4 * (rb & 1) + v] = to_bf16(fast_tanh(d[v]));
     }
     floatx4 d = c3;
-    for (int kb = 0; kb < 4; kb++)
-      d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[kb], b3[kb], d, 0, 0, 0);
+    for (int kb = 0; kb < 2; kb++)
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[kb], b3[kb], d, 0, 0, 0);
     // lanes 0..15 hold the three outputs of point m in d[0..2]
     if (lane < 16 && ok) {
       if (a.y)
@@ -386,7 +421,8 @@ void run_infer(iblbm_ctx* c, float* y_out) {
   a.dF = c->mdF;
   a.fp64 = c->fp64;
   a.y = y_out;
-  int waves = std::min((c->nmk + 15) / 16, 256 * 16);
+  // three waves per SIMD fit the kernel's registers: 256 CUs x 4 SIMDs x 3
+  int waves = std::min((c->nmk + 15) / 16, INFER_WAVES);
   hipLaunchKernelGGL(k_mlp_infer, dim3((waves + 3) / 4), dim3(256), 0, c->stream, a);
 }
 
@@ -567,7 +603,7 @@ iblbm_status iblbm_nn_forward(const float* x, int64_t n, const float* params, fl
   a.dF = nullptr;
   a.fp64 = 0;
   a.y = dY;
-  int waves = (int)std::min<int64_t>((n + 15) / 16, 256 * 16);
+  int waves = (int)std::min<int64_t>((n + 15) / 16, INFER_WAVES);
   hipLaunchKernelGGL(k_mlp_infer, dim3((waves + 3) / 4), dim3(256), 0, 0, a);
   if (hipMemcpy(y, dY, (size_t)n * NO * 4, hipMemcpyDeviceToHost) != hipSuccess) return IBLBM_E_DEVICE;
   return IBLBM_OK;

@@ -134,7 +134,8 @@ def reduce_(args):
             f"rocprofv3 --pmc {c} -f csv -d <dir> -o run -- python -m paper_2002_08855_amd.traffic "
             f"run --workload {args.workload} --steps {args.steps}" for c in ("FETCH_SIZE", "WRITE_SIZE")
         ] + [f"python -m paper_2002_08855_amd.traffic reduce --fetch <dir> --write <dir> "
-             f"--workload {args.workload} --kernel {args.kernel} --steps {args.steps} --out {args.out}"],
+             f"--workload {args.workload} --kernel {args.kernel} --steps {args.steps} "
+             f"--out profiles/{args.kernel}_{args.workload}_pmc.json"],
     }
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)

@@ -76,3 +76,47 @@ def test_full_size_parity(name, steps):
         assert e[k] < 1e-5, (k, e[k])
     for k in ("U", "X_disp"):
         assert e[k] < 1e-4, (k, e[k])
+
+
+def _bf16(a):
+    """round to BF16 (nearest even) and back, as the GPU stores the weights"""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_full_size_learned_step_parity():
+    """The 256^3 learned-forcing workload (2347 spheres D=16, 804 points each, volume
+    fraction 0.30): one plain MDF-5 step, then two learned steps (MLP prediction, one
+    correction pass, the slip judge), GPU with BF16 MFMA inference against the FP64 oracle
+    on the same BF16-rounded weights.  The weights give O(1) outputs and the output scale
+    is the converged force of this state (from the oracle's capture), so the prediction
+    carries the boundary force.  Bound: 2^-6 relative, eight BF16 unit roundoffs, as for
+    the small learned-step case."""
+    b = _gpu()
+    w = inputs.workload("cavity256_learned")
+    p, parts = dict(w["params"]), w["particles"]
+    p["slip_tol"] = 1e30  # the learned path on both sides, never the fallback
+    t0 = time.time()
+    g, o = b.Sim(p), oracle.Sim(p)
+    for s in (g, o):
+        s.add_particles(parts["center"], parts["diameter"], parts["density"],
+                        n_markers=parts["n_markers"])
+        s.step(1)  # no MLP installed yet: plain MDF-5
+    f, t = o.capture_samples()
+    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    P = _bf16(np.random.default_rng(11).normal(0.0, 0.3, oracle.NPARAM))
+    y = oracle.mlp_forward(P, (f - norm[:10]) / norm[10:20])
+    print("MLP output std", y.std(0), round(time.time() - t0, 1), "s", flush=True)
+    assert np.all(y.std(0) > 0.3)
+    for s in (g, o):
+        s.set_mlp(P, norm)
+        s.step(2)
+    e = {}
+    for k, a_, r_ in zip(("p", "u", "force"), g.fields(), o.fields()):
+        e[k] = rel_l2(a_, r_)
+    e["U"] = rel_l2(g.particles()["U"], o.particles()["U"])
+    print("learned 256^3 after 2 learned steps:", e, round(time.time() - t0, 1), "s", flush=True)
+    for k, v in e.items():
+        assert v < 2.0 ** -6, (k, v)

@@ -139,3 +139,57 @@ def test_f16_scale_power_of_two_roundtrip():
     g2.set_pdfs(f0)
     f2 = g2.get_pdfs()
     assert np.max(np.abs(f2 - f0) / np.maximum(np.abs(f0), 1e-30)) <= 2.0 ** -8 * 1.01
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_384(steps):
+    w = inputs.workload("cavity384_bf16")
+    p, parts = dict(w["params"], storage="f64"), w["particles"]
+    o = oracle.Sim(p)
+    o.add_particles(parts["center"], parts["diameter"], parts["density"],
+                    n_markers=parts["n_markers"])
+    for k in range(steps):  # one to two minutes per step on 16 host threads
+        o.step(1)
+        print(f"oracle 384^3 step {k + 1} of {steps}", flush=True)
+    res = o.fields(), o.particles()["U"]
+    del o
+    return res
+
+
+@pytest.mark.skipif(not os.environ.get("IBLBM_FULL_384"),
+                    reason="the FP64 oracle at 384^3 takes several minutes and about 20 GB of "
+                           "host memory; set IBLBM_FULL_384=1 to run it")
+@pytest.mark.parametrize("storage,bound", [("f16", 5e-3), ("bf16", 3e-2)])
+def test_storage_error_at_384_full_size(storage, bound):
+    """The 384^3 workload itself (25033 spheres D=12, 452 points, volume fraction 0.40)
+    with 16-bit PDF storage against the FP64 oracle over 3 steps (the flow starts in the
+    second): errors over the whole lattice and over its centre 64^3 crop [160, 224)^3,
+    within the same sanity bounds as the 64^3 stand-in."""
+    b = _gpu()
+    steps = 3
+    (po, uo, fo), Uo = _oracle_384(steps)
+    w = inputs.workload(f"cavity384_{storage}")
+    p, parts = w["params"], w["particles"]
+    g = b.Sim(p)
+    g.add_particles(parts["center"], parts["diameter"], parts["density"],
+                    n_markers=parts["n_markers"])
+    g.step(steps)
+    pg, ug, fg = g.fields()
+    n = p["n"]
+
+    def crop(a):
+        a = a.reshape(a.shape[:-1] + (n[2], n[1], n[0]))
+        return a[..., 160:224, 160:224, 160:224]
+
+    err = {"steps": steps, "case": "384^3, 25033 spheres D=12 (phi 0.40)"}
+    for k, a_, r_ in (("p", pg, po), ("u", ug, uo), ("force", fg, fo)):
+        err[k] = rel_l2(a_, r_)
+        err[k + "_crop"] = rel_l2(crop(a_), crop(r_))
+    err["U"] = rel_l2(g.particles()["U"], Uo)
+    print(storage, json.dumps(err))
+    if OUT:
+        os.makedirs(OUT, exist_ok=True)
+        with open(os.path.join(OUT, f"precision_384_{storage}.json"), "w") as fh:
+            json.dump(err, fh)
+    for k in ("u", "force", "u_crop", "force_crop", "U"):
+        assert err[k] < bound, (k, err[k])
