@@ -37,6 +37,11 @@ PMC_KERNEL = {"collide": "k_collide_stream", "band": "k_ustar_all", "interp": "k
 MLP_FLOP_PER_POINT = 2 * (10 * 64 + 64 * 64 + 64 * 3)
 
 
+def progress(msg):
+    """a progress line on stderr (the JSON result stays alone on stdout)"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(group, p, nmk, band_nodes):
     """Bytes one launch of a kernel group must move, as the survey's measurement section
     defines them (f_0, padding and the method's own bookkeeping not credited):
@@ -146,8 +151,10 @@ def run(args):
                         "avg_launch_ms": round(ms_c, 5), "algorithmic_bytes_per_launch": int(nb_c)}
     del sim
     torch.cuda.empty_cache()
+    progress(f"{args.workload}: {mlups:.1f} MLUPS over {args.steps} steps")
     # the slip statistic needs particles; particle-free workloads report none
-    slip = slip_run(binding, w, int(w.get("steps", 500))) if parts is not None else None
+    slip_steps = int(w.get("steps", 500)) if args.slip_steps is None else args.slip_steps
+    slip = slip_run(binding, w, slip_steps) if parts is not None and slip_steps > 0 else None
     out = {
         "metric": "MLUPS at phi=0.40 (plain FP32 vs BF16-PDF / learned forcing) at stated slip error",
         "value": round(mlups, 1),
@@ -248,8 +255,9 @@ def run_forms(args, only=None):
     - learned forcing (256^3, 2347 spheres, 0.30) against plain MDF-5 and against MDF-2,
       the plain method with the same number of spreading passes.  The network is trained
       here, on the GPU, on (features, converged MDF-5 force) pairs captured from plain runs
-      of a different workload (cavity256_train: 1565 spheres, 0.20, its own seed), so the
-      evaluation set is held out.
+      of two other packings (cavity256_train: 1565 spheres, 0.20, random addition;
+      cavity256_train30: 2347 spheres, 0.30, a finer FCC lattice; each with its own seed),
+      so the evaluation set is held out.
     Each form reports MLUPS over timed steps and the slip averaged over the last half of
     a run of the workload's length.  `only` names one form to run by itself (for a
     profiler run)."""
@@ -271,8 +279,9 @@ def run_forms(args, only=None):
         np_, nmk = sim.counts()
         del sim
         torch.cuda.empty_cache()
-        r["slip"] = slip_run(binding, w, int(w.get("steps", 200)), params=p, mlp=mlp)
-        r["slip_rms"] = r["slip"]["slip_rms"]
+        n_slip = int(w.get("steps", 200)) if args.slip_steps is None else args.slip_steps
+        r["slip"] = slip_run(binding, w, n_slip, params=p, mlp=mlp) if n_slip > 0 else None
+        r["slip_rms"] = r["slip"]["slip_rms"] if r["slip"] else None
         r.update({"workload": name, "particles": np_, "points": nmk})
         return r
 
@@ -308,33 +317,42 @@ def run_forms(args, only=None):
             forms[name] = fn()
         except Exception as e:  # reported, not fatal for the headline line
             forms[name] = {"error": repr(e)}
+        progress(f"form {name} done")
     return forms
 
 
 def learned_form(binding, inputs, measure, warmup):
-    """Train on captures of the plain cavity256_train runs (held out), evaluate on
-    cavity256_learned: learned + 1 correction pass, plain MDF-5 and plain MDF-2."""
+    """Train on captures of plain MDF-5 runs of two other packings (cavity256_train and
+    cavity256_train30), evaluate on cavity256_learned, held out: learned + 1 correction
+    pass, plain MDF-5 and plain MDF-2."""
     import numpy as np
 
-    wt = inputs.workload("cavity256_train")
-    sim = _sim(binding, wt["params"], wt["particles"])
-    # captures spread over the same 200 steps from rest that the evaluation run covers
+    # captures spread over the same 200 steps from rest that the evaluation run covers,
+    # from two training packings (0.20 by random addition, 0.30 on a finer FCC lattice)
     feats, tgts = [], []
-    for _ in range(10):
-        sim.step(20)
-        f, t = sim.capture_samples()
-        feats.append(f)
-        tgts.append(t)
-    del sim
+    train_sets = ("cavity256_train", "cavity256_train30")
+    for name in train_sets:
+        wt = inputs.workload(name)
+        sim = _sim(binding, wt["params"], wt["particles"])
+        for _ in range(10):
+            sim.step(20)
+            f, t = sim.capture_samples()
+            feats.append(f)
+            tgts.append(t)
+        del sim
     f = np.concatenate(feats)
     t = np.concatenate(tgts)
-    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    # the network's target: the change of the converged force over the previous step's
+    r = t - f[:, 3:6]
+    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, r.mean(0), r.std(0) + 1e-12])
     xn = (f - norm[:10]) / norm[10:20]
-    tn = (t - norm[20:23]) / norm[23:26]
+    tn = (r - norm[20:23]) / norm[23:26]
     P0 = np.random.default_rng(1).normal(0, 0.1, binding.NPARAM)
     epochs = 8
+    progress(f"learned form: {len(f)} training samples captured")
     t0 = time.perf_counter()
     P, curve = binding.nn_train(xn, tn, P0, epochs=epochs, batch=8192, lr=2e-3, seed=1)
+    progress(f"learned form: trained in {time.perf_counter() - t0:.1f} s")
     train_s = time.perf_counter() - t0
     w = inputs.workload("cavity256_learned")
     base = dict(w["params"])
@@ -351,7 +369,7 @@ def learned_form(binding, inputs, measure, warmup):
                           "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
                           "frac": round(flops / (t_mlp * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 6)}
     rl.update({"dtype": "f32, MLP in bf16 on MFMA", "correction_passes": 1,
-               "train": {"workload": "cavity256_train", "samples": int(len(f)),
+               "train": {"workloads": list(train_sets), "samples": int(len(f)),
                          "captures": len(feats), "epochs": epochs,
                          "seconds": round(train_s, 2), "loss_first": float(curve[0]),
                          "loss_last": float(curve[-1])},
@@ -524,6 +542,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16-storage and learned-forcing forms")
     ap.add_argument("--form-steps", type=int, default=20)
+    ap.add_argument("--slip-steps", type=int, default=None,
+                    help="length of the run the slip is averaged over (default: the "
+                         "workload's run length; 0 skips it, e.g. under a profiler)")
     ap.add_argument("--form", choices=["bf16_storage", "btdf_single_pass", "learned_forcing"],
                     help="instead of the headline line: run one form by itself")
     ap.add_argument("--sweep", action="store_true",

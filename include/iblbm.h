@@ -42,7 +42,8 @@ typedef enum {
   IBLBM_E_DEVICE = 3,   /* a HIP call failed */
   IBLBM_E_STATE = 4,    /* the context is in a sticky error state */
   IBLBM_E_UNSTABLE = 5, /* NaN/Inf detected in the fluid or particle state */
-  IBLBM_E_CAPACITY = 6  /* a fixed-capacity list (cell list, pair list) overflowed */
+  IBLBM_E_CAPACITY = 6, /* a fixed-capacity list (pair list, scratch) overflowed */
+  IBLBM_E_CELL_OVERFLOW = 7 /* more centres in one search cell than it holds (Eq. 49) */
 } iblbm_status;
 
 typedef enum { IBLBM_F64 = 0, IBLBM_F32 = 1, IBLBM_BF16 = 2, IBLBM_F16 = 3 } iblbm_storage;
@@ -143,11 +144,13 @@ iblbm_status iblbm_add_particles(iblbm_ctx* ctx, int32_t n, const double* center
                                  int32_t markers_per_particle);
 
 /* Advance nsteps time steps; returns after the work is enqueued and the status word has
- * been read back (one device synchronisation per call).  A particle faster than one
+ * been read back (one device synchronisation per call; with learned forcing and no graph,
+ * also one per step, where the host reads the slip check's verdict before it launches the
+ * MDF fallback only when that is needed).  A particle faster than one
  * lattice unit per step (or NaN) stops the particle and IB kernels of the remaining steps
  * of the call; the call then returns IBLBM_E_UNSTABLE and the context refuses to step
  * again (the getters still read the state).  Cell or pair lists that overflow their
- * capacity return IBLBM_E_CAPACITY. */
+ * capacity return IBLBM_E_CELL_OVERFLOW (a cell) or IBLBM_E_CAPACITY (a pair list). */
 iblbm_status iblbm_step(iblbm_ctx* ctx, int32_t nsteps);
 
 /* p (Eq. 6) and u* (Eq. 5) of the current PDFs (N and dim*N values) and the IB force
@@ -158,11 +161,14 @@ iblbm_status iblbm_get_fields(iblbm_ctx* ctx, double* p, double* u, double* forc
  * density of each surface point at the last step. */
 iblbm_status iblbm_get_forces(iblbm_ctx* ctx, double* X, double* U, double* Omega,
                               double* F_h, double* T_h, double* F_c, double* marker_F);
-/* Pairs i<j with |Xi-Xj|^2 < ((Di+Dj)/2 + zeta)^2 at the positions of the last step
- * (or of iblbm_add_particles), sorted; *n_pairs receives the count even when it
- * exceeds cap. */
+/* The particle pairs of the collision search (Table 4's pairs, found through the cell
+ * grid of Table 5): pairs i<j with |Xi-Xj|^2 < ((Di+Dj)/2 + zeta)^2 at the positions of
+ * the last step (or of iblbm_add_particles), sorted, as 2 int32 per pair into ij (host,
+ * caller-owned, room for cap pairs); *n_pairs receives the count even when it exceeds
+ * cap (then only cap pairs are written). */
 iblbm_status iblbm_get_pairs(iblbm_ctx* ctx, int32_t* ij, int64_t cap, int64_t* n_pairs);
-/* Cell coordinates (np*3) of every particle at the last step, and the cell-grid size. */
+/* The search cells of Eqs. 49-51 (Table 5): cell coordinates (np*3 int32, host,
+ * caller-owned) of every particle at the last step, and the cell-grid size (3 int32). */
 iblbm_status iblbm_get_cells(iblbm_ctx* ctx, int32_t* cell, int32_t* dims);
 iblbm_status iblbm_get_stats(iblbm_ctx* ctx, iblbm_stats* out);
 iblbm_status iblbm_num_particles(iblbm_ctx* ctx, int32_t* np, int32_t* n_markers);
@@ -206,7 +212,10 @@ iblbm_status iblbm_set_graph(iblbm_ctx* ctx, int32_t on);
 
 /* Learned forcing (MLP 10-64-64-3 with tanh hidden layers).  params: 5059 floats
  * W1[64][10], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]; norm: 26 floats (feature
- * mean[10], feature std[10], target mean[3], target std[3]). */
+ * mean[10], feature std[10], then the mean[3] and std[3] of the network's target, the
+ * change F - F_prev of a point's converged force over the previous step's).  A point's
+ * predicted force is F_prev + mean + std * y, y the network's output on the normalised
+ * features.  Host arrays, copied; IBLBM_E_NOMEM if the device copy cannot be allocated. */
 iblbm_status iblbm_set_mlp(iblbm_ctx* ctx, const float* params, const float* norm);
 /* Features (n_markers*10: pass-0 slip, previous-step force, unit normal, gap clamped
  * to [0, zeta]) and converged MDF force after mdf_iters passes (n_markers*3) at the

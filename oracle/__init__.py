@@ -95,6 +95,7 @@ def load(path):
             "ref_truncated": (C.c_int64, [C.c_void_p]),
             "ref_fallbacks": (C.c_int32, [C.c_void_p]),
             "ref_mlp_forward": (None, [_d, C.c_int64, _d, _d]),
+            "ref_mlp_predict": (None, [_d, _d, C.c_int64, C.c_int32, _d, _d, _d]),
             "ref_mlp_loss_grad": (C.c_double, [_d, C.c_int64, _d, _d, _d]),
             "ref_set_mlp": (C.c_int32, [C.c_void_p, _d, _d]),
             "ref_capture_samples": (C.c_int32, [C.c_void_p, _d, _d]),
@@ -237,6 +238,18 @@ def mlp_forward(params, x):
     y = np.zeros((x.shape[0], 3))
     lib().ref_mlp_forward(_dp(params), x.shape[0], _dp(x), _dp(y))
     return y
+
+
+def mlp_predict(params, norm, feat, Fprev, dim=3, L=None):
+    """the learned force F = F_prev + target mean + target std * MLP(normalised features)"""
+    params = _f64(params)
+    norm = _f64(norm)
+    feat = _f64(feat, (-1, 10))
+    Fprev = _f64(Fprev, (-1, 3))
+    F = np.zeros((feat.shape[0], 3))
+    (L or lib()).ref_mlp_predict(_dp(params), _dp(norm), feat.shape[0], dim, _dp(feat),
+                                 _dp(Fprev), _dp(F))
+    return F
 
 
 def mlp_loss_grad(params, x, t):

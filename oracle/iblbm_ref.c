@@ -767,9 +767,11 @@ static void ibm_stage(ref_ctx* c) {
     memset(c->fib, 0, sizeof(double) * 3 * (size_t)N);
     for (int m = 0; m < 3 * c->nmk; m++) c->mF[m] = 0.0;
     forcing_pass(c, Fp);
+    /* the judge: the slip the prediction leaves, which the correction pass then corrects */
+    double judged = slip_rms(c);
     forcing_pass(c, NULL);
     c->slip = slip_rms(c);
-    if (!(c->slip <= c->cfg.slip_tol)) {
+    if (!(judged <= c->cfg.slip_tol)) {
       mdf(c, c->cfg.fallback_iters);
       c->slip = slip_rms(c);
       c->fallbacks++;
@@ -1392,21 +1394,26 @@ static void features(ref_ctx* c, double* feat) {
   }
 }
 
-static void mlp_apply(ref_ctx* c, const double* feat, double* Fout) {
-  const double* mean = c->norm;
-  const double* sd = c->norm + NI;
-  const double* tmean = c->norm + 2 * NI;
-  const double* tsd = c->norm + 2 * NI + NO;
-  double* xn = (double*)xcalloc((size_t)NI * c->nmk, sizeof(double));
-  double* y = (double*)xcalloc((size_t)NO * c->nmk, sizeof(double));
-  for (int m = 0; m < c->nmk; m++)
+void ref_mlp_predict(const double* params, const double* norm, int64_t n, int32_t dim,
+                     const double* feat, const double* Fprev, double* F) {
+  const double* mean = norm;
+  const double* sd = norm + NI;
+  const double* tmean = norm + 2 * NI;
+  const double* tsd = norm + 2 * NI + NO;
+  double* xn = (double*)xcalloc((size_t)NI * (size_t)(n > 0 ? n : 1), sizeof(double));
+  double* y = (double*)xcalloc((size_t)NO * (size_t)(n > 0 ? n : 1), sizeof(double));
+  for (int64_t m = 0; m < n; m++)
     for (int i = 0; i < NI; i++) xn[NI * m + i] = (feat[NI * m + i] - mean[i]) / sd[i];
-  ref_mlp_forward(c->mlp, c->nmk, xn, y);
-  for (int m = 0; m < c->nmk; m++)
+  ref_mlp_forward(params, n, xn, y);
+  for (int64_t m = 0; m < n; m++)
     for (int o = 0; o < 3; o++)
-      Fout[3 * m + o] = o < c->dim ? y[NO * m + o] * tsd[o] + tmean[o] : 0.0;
+      F[3 * m + o] = o < dim ? Fprev[3 * m + o] + (tmean[o] + tsd[o] * y[NO * m + o]) : 0.0;
   free(xn);
   free(y);
+}
+
+static void mlp_apply(ref_ctx* c, const double* feat, double* Fout) {
+  ref_mlp_predict(c->mlp, c->norm, c->nmk, c->dim, feat, c->mFprev, Fout);
 }
 
 int32_t ref_capture_samples(ref_ctx* c, double* feat, double* target) {

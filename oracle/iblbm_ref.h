@@ -139,9 +139,15 @@ int32_t ref_fallbacks(const ref_ctx* c);
 #define REF_MLP_OUT 3
 #define REF_MLP_NPARAM (REF_MLP_IN*REF_MLP_H + REF_MLP_H + REF_MLP_H*REF_MLP_H + REF_MLP_H + REF_MLP_H*REF_MLP_OUT + REF_MLP_OUT)
 /* params: W1[64][10], b1[64], W2[64][64], b2[64], W3[3][64], b3[3] (row-major, out x in)
- * norm: feature mean[10], feature std[10], target mean[3], target std[3] */
+ * norm: feature mean[10], feature std[10], then the mean[3] and std[3] of the change of
+ * the converged force over the previous step's, F - F_prev (the network's target) */
 void ref_mlp_forward(const double* params, int64_t n, const double* x /* n*10, normalised */,
                      double* y /* n*3 */);
+/* the learned force of n points: F = F_prev + target mean + target std * y, with y the
+ * network's output on the normalised features (feat n*10 raw, Fprev n*3, F n*3; the
+ * components past dim are 0) */
+void ref_mlp_predict(const double* params, const double* norm, int64_t n, int32_t dim,
+                     const double* feat, const double* Fprev, double* F);
 /* loss = mean over n*3 of (y - t)^2; grad (NPARAM) of that loss */
 double ref_mlp_loss_grad(const double* params, int64_t n, const double* x, const double* t,
                          double* grad);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libiblbm.so")
 
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSTABLE",
-          6: "E_CAPACITY"}
+          6: "E_CAPACITY", 7: "E_CELL_OVERFLOW"}
 NPARAM = 10 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 TIMERS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
 

@@ -173,6 +173,7 @@ struct iblbm_ctx {
   std::vector<double> hmr;    // host copy of the point offsets (4 per point)
   uint16_t* tlist = nullptr;  // npatch x box_cap: touched box nodes of each unit, ascending
   int* tcount = nullptr;      // npatch: entries of tlist per unit
+  double* slip_part = nullptr;  // npatch: per-unit sums of the slip statistic
   // status and statistics
   int* dstatus = nullptr;     // [0] flags, [1] truncated (int64 at [2..3]), ...
   double* dstats = nullptr;   // [0] slip sum of squares
@@ -204,6 +205,9 @@ struct iblbm_ctx {
   bool gend_band_pending[4] = {false, false, false, false};
   bool gend_ustar_valid[4] = {false, false, false, false};
   bool graph_dirty = true;
+  bool capturing = false;  // enqueue_step is being recorded into a graph
+  int* hflag = nullptr;          // pinned host word: the learned step's fallback verdict
+  hipEvent_t ev_flag = nullptr;  // recorded once the verdict has been copied to hflag
   // allocations
   std::vector<void*> allocs;
 };
@@ -250,4 +254,12 @@ void mlp_infer(iblbm_ctx* c);
 
 // timing helpers (host.hip)
 void tbegin(iblbm_ctx* c, int group);
+// a failed HIP call inside a step: records the error on the context and unwinds the
+// step (to the entry point, which returns IBLBM_E_DEVICE)
+void hip_check(iblbm_ctx* c, hipError_t e, const char* expr);
+// one int from device memory, read on the context's stream (waits for the stream)
+int read_device_int(iblbm_ctx* c, const int* d);
+// device memory through the caller's allocator callbacks when given (else hipMalloc),
+// released with the context; nullptr (and the context's error set) on failure
+void* ctx_alloc(iblbm_ctx* c, size_t bytes);
 void tend(iblbm_ctx* c);

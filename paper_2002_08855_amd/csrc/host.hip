@@ -370,8 +370,11 @@ void step_graph(iblbm_ctx* c) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     try {
+      c->capturing = true;
       enqueue_step(c);
+      c->capturing = false;
     } catch (...) {
+      c->capturing = false;
       (void)hipStreamEndCapture(c->stream, &g);
       if (g) (void)hipGraphDestroy(g);
       throw;
@@ -397,6 +400,26 @@ void step_graph(iblbm_ctx* c) {
 }
 
 }  // namespace
+
+void hip_check(iblbm_ctx* c, hipError_t e, const char* expr) {
+  if (e != hipSuccess)
+    throw Fail{fail(c, IBLBM_E_DEVICE, std::string(expr) + ": " + hipGetErrorString(e))};
+}
+
+void* ctx_alloc(iblbm_ctx* c, size_t bytes) {
+  try {
+    return dalloc(c, bytes);
+  } catch (const Fail&) {
+    return nullptr;
+  }
+}
+
+int read_device_int(iblbm_ctx* c, const int* d) {
+  int v = 0;
+  HIPCHK(hipMemcpyAsync(&v, d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return v;
+}
 
 void tbegin(iblbm_ctx* c, int group) {
   c->t_open = false;
@@ -504,6 +527,8 @@ void iblbm_destroy(iblbm_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_flag) (void)hipEventDestroy(c->ev_flag);
+  if (c->hflag) (void)hipHostFree(c->hflag);
   drop_graphs(c);
   std::vector<void*> all = c->allocs;
   for (void* p : all) dfree(c, p);
@@ -722,8 +747,10 @@ iblbm_status iblbm_add_particles(iblbm_ctx* c, int32_t n, const double* center,
     build_patches(c);
     if (c->tlist) dfree(c, c->tlist);
     if (c->tcount) dfree(c, c->tcount);
+    if (c->slip_part) dfree(c, c->slip_part);
     c->tlist = dzeros<uint16_t>(c, (size_t)c->npatch * (c->box_cap <= 65536 ? c->box_cap : 1));
     c->tcount = dzeros<int>(c, (size_t)c->npatch);
+    c->slip_part = dzeros<double>(c, (size_t)c->npatch);
     c->cell_of = dzeros<int>(c, 3 * (size_t)np);
     c->pair_up = dzeros<int>(c, (size_t)np * PAIR_CAP);
     c->pair_nup = dzeros<int>(c, (size_t)np);
@@ -771,8 +798,10 @@ iblbm_status iblbm_step(iblbm_ctx* c, int32_t nsteps) {
       c->slip_rms = sqrt(s2 / c->nmk);
     }
     if (flags & ST_NAN) return fail(c, IBLBM_E_UNSTABLE, "NaN/Inf or runaway particle velocity");
-    if (flags & (ST_CELL_OVERFLOW | ST_PAIR_OVERFLOW))
-      return fail(c, IBLBM_E_CAPACITY, "cell or pair list capacity exceeded");
+    if (flags & ST_CELL_OVERFLOW)
+      return fail(c, IBLBM_E_CELL_OVERFLOW, "more particle centres in a search cell than it holds");
+    if (flags & ST_PAIR_OVERFLOW)
+      return fail(c, IBLBM_E_CAPACITY, "pair list capacity exceeded");
   } catch (Fail& e) {
     return e.st;
   }

@@ -82,10 +82,20 @@ struct InterpArgs {
 // mode 0: a multi-direct-forcing pass (Eqs. 9-10): dF = 2 rho0 (U_b - D_I u), F += dF.
 // mode 1: accumulate |U_b - D_I u|^2 for the slip statistic.
 // mode 2: write U_b - D_I u into the learned-force features.
+// mode 3: mode 0 and mode 1 at once (the correction pass of the learned step, whose
+//         slip judges the prediction).
 template <class C>
 __device__ __forceinline__ void point_result(const InterpArgs<C>& a, int k, const double* Ub,
                                              const C* acc, int DIM) {
-  if (a.mode == 0) {
+  if (a.mode == 3) {
+    double s = 0;
+    for (int c = 0; c < DIM; c++) {
+      double e = Ub[c] - double(acc[c]);
+      s += e * e;
+    }
+    atomicAdd(a.slip2, s);
+  }
+  if (a.mode == 0 || a.mode == 3) {
     C* F = a.F + 4 * (size_t)k;
     C* dF = a.dF + 4 * (size_t)k;
     for (int c = 0; c < DIM; c++) {
@@ -259,6 +269,9 @@ __global__ void k_reset_count(int* count) { *count = 0; }
 // ---------------------------------------------------------------------------
 // per-particle kernels
 
+// static LDS of the interpolation kernel beside its dynamic box: one double per wavefront
+constexpr size_t INTERP_STATIC_LDS = (LDS_THREADS / 64) * sizeof(double);
+
 template <class C>
 struct LdsArgs {
   MarkerGeo g;
@@ -282,6 +295,7 @@ struct LdsArgs {
   int mcap;        // points of the largest particle
   uint16_t* tlist; // touched box nodes per work unit (cap entries each), ascending
   int* tcount;
+  double* slip_part;  // per-unit sums of |U_b - D_I u|^2 (interpolation modes 1 and 3)
   // work units: with patched == 0 the unit is the particle (box of +-D/2); otherwise
   // unit q is the run of pt_mc[q] points from pt_m0[q] of particle pt_owner[q], with the
   // box of the offset range [pt_rlo, pt_rhi]
@@ -477,7 +491,10 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   PBox<DIM> b;
   unit_of<DIM>(a, q, p, m0, mc, b);
   // the host sizes cap and the block for the largest unit
-  if (stop || b.n > a.cap || mc > (int)blockDim.x) return;
+  if (stop || b.n > a.cap || mc > (int)blockDim.x) {
+    if ((a.mode == 1 || a.mode == 3) && threadIdx.x == 0) a.slip_part[q] = 0.0;
+    return;
+  }
   // this lane's point, loaded and weighted before the box is staged so that the
   // latencies overlap; with an accumulating pass also its force so far
   const int k = m0 + (int)threadIdx.x;
@@ -487,7 +504,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   C Fold[3] = {C(0), C(0), C(0)};
   if (has) {
     marker_pos_vel(a.P, k, X, Ub, DIM);
-    if (a.mode == 0 && !a.first_pass) {
+    if ((a.mode == 0 || a.mode == 3) && !a.first_pass) {
 #pragma unroll
       for (int c = 0; c < DIM; c++) Fold[c] = a.F[4 * (size_t)k + c];
     }
@@ -573,13 +590,20 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
   __syncthreads();
   // gather each support from LDS (Eq. 9 with Eq. 12) and form the point force (Eq. 10)
   unsigned long long ntr = 0;
+  double s2 = 0.0;  // mode 1: this lane's |U_b - D_I u|^2
   if (has) {
     C acc[3] = {0, 0, 0};
     ntr += visit_support<DIM, C>(a.g, b, pw, [&](int loc, C w) {
 #pragma unroll
       for (int c = 0; c < DIM; c++) acc[c] += w * ub[c * a.cap + loc];
     });
-    if (a.mode == 0) {
+    if (a.mode == 1 || a.mode == 3) {
+      for (int c = 0; c < DIM; c++) {
+        double e = Ub[c] - double(acc[c]);
+        s2 += e * e;
+      }
+    }
+    if (a.mode == 0 || a.mode == 3) {
       C* F = a.F + 4 * (size_t)k;
       C* dF = a.dF + 4 * (size_t)k;
       for (int c = 0; c < DIM; c++) {
@@ -587,16 +611,23 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
         dF[c] = d;
         F[c] = a.first_pass ? d : Fold[c] + d;
       }
-    } else if (a.mode == 1) {
-      double s2 = 0;
-      for (int c = 0; c < DIM; c++) {
-        double e = Ub[c] - double(acc[c]);
-        s2 += e * e;
-      }
-      atomicAdd(a.slip2, s2);
-    } else {
+    } else if (a.mode == 2) {
       for (int c = 0; c < 3; c++)
         a.feat[10 * (size_t)k + c] = c < DIM ? float(Ub[c] - double(acc[c])) : 0.f;
+    }
+  }
+  if (a.mode == 1 || a.mode == 3) {
+    // the unit's sum, over each wavefront (blocks are whole wavefronts) and then over the
+    // wavefronts in order, stored for a fixed-order sum over the units: atomics on the
+    // one global word serialise (about 9 ns each at 256^3), and the order is fixed
+    __shared__ double wsum[INTERP_STATIC_LDS / sizeof(double)];
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += wsum[w];
+      a.slip_part[q] = t;
     }
   }
   if (a.first_pass && a.mode == 0 && ntr) atomicAdd(a.trunc, ntr);
@@ -768,6 +799,21 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   }
 }
 
+// slip2 += the per-unit sums, in unit order (one block)
+__global__ __launch_bounds__(256) void k_sum_units(const double* part, int n, double* slip2) {
+  __shared__ double red[256];
+  double t = 0.0;
+  const int per = (n + 255) / 256, lo = threadIdx.x * per;
+  for (int i = lo; i < lo + per && i < n; i++) t += part[i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < 256; k++) s += red[k];
+    *slip2 += s;
+  }
+}
+
 // Fallback band u*: at the nodes of every listed segment compute u* from the PDFs,
 // clear the force, and mark the segment's nodes in the band bitmap.
 template <int DIM, class T, int PAR>
@@ -884,6 +930,7 @@ LdsArgs<typename Store<T>::C> make_lds_args(iblbm_ctx* c, int first, int mode) {
   a.mcap = max_points(c);
   a.tlist = c->tlist;
   a.tcount = c->tcount;
+  a.slip_part = c->slip_part;
   a.patched = c->patched ? 1 : 0;
   a.pt_owner = c->pt_owner;
   a.pt_m0 = c->pt_m0;
@@ -934,9 +981,11 @@ void raise_lds_limit(const void* k, int bytes) {
 template <int DIM, class T>
 struct RunInterp {
   static void limits(iblbm_ctx* c) {
-    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 0>, c->lds_max);
-    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 1>, c->lds_max);
-    raise_lds_limit((const void*)k_interp_lds<DIM, T, 1, 1>, c->lds_max);
+    // the dynamic limit leaves room for the kernel's static LDS
+    const int dyn = c->lds_max - (int)INTERP_STATIC_LDS;
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 0>, dyn);
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 1>, dyn);
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 1, 1>, dyn);
   }
   static void run(iblbm_ctx* c, int first, int mode, bool* done) {
     using C = typename Store<T>::C;
@@ -958,8 +1007,11 @@ struct RunInterp {
     // later passes stage from the step's list: only the velocity box is needed
     if (!FIRST) bytes = ((size_t)DIM * c->box_cap * sizeof(C) + 7) & ~(size_t)7;
     auto k = k_interp_lds<DIM, T, PAR, FIRST>;
-    raise_lds_limit((const void*)k, c->lds_max);
+    raise_lds_limit((const void*)k, c->lds_max - (int)INTERP_STATIC_LDS);
     hipLaunchKernelGGL(k, dim3(c->npatch), dim3(interp_threads(c)), bytes, c->stream, a);
+    if (a.mode == 1 || a.mode == 3)
+      hipLaunchKernelGGL(k_sum_units, dim3(1), dim3(256), 0, c->stream, c->slip_part, c->npatch,
+                         c->dstats);
   }
 };
 
@@ -1041,7 +1093,7 @@ bool ibm_uses_lds(const iblbm_ctx* c) {
   size_t cs = c->fp64 ? 8 : 4;
   return c->ibm_lds && c->patch_ok && c->box_cap > 0 && c->box_cap <= 65536 &&
          max_points(c) <= LDS_THREADS &&
-         lds_bytes(c, cs, true) <= (size_t)c->lds_max &&
+         lds_bytes(c, cs, true) + INTERP_STATIC_LDS <= (size_t)c->lds_max &&
          lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
 

@@ -56,6 +56,7 @@ struct InferArgs {
   int dim;
   void* F;   // n x 4 compute type (set to the prediction)
   void* dF;  // n x 4 compute type
+  const void* Fprev;  // n x 4 compute type: the previous step's force
   int fp64;
   float* y;  // optional n x 3 raw outputs (normalised units)
 };
@@ -163,12 +164,15 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
       if (a.y)
         for (int o = 0; o < NO; o++) a.y[(size_t)m * NO + o] = d[o];
       if (a.F) {
+        // the network predicts the change over the previous step's force
         for (int o = 0; o < 3; o++) {
-          float val = o < a.dim ? d[o] * tsd[o] + tmean[o] : 0.f;
+          const float dv = tmean[o] + tsd[o] * d[o];
           if (a.fp64) {
+            const double val = o < a.dim ? ((const double*)a.Fprev)[4 * (size_t)m + o] + double(dv) : 0.0;
             ((double*)a.F)[4 * (size_t)m + o] = val;
             ((double*)a.dF)[4 * (size_t)m + o] = val;
           } else {
+            const float val = o < a.dim ? ((const float*)a.Fprev)[4 * (size_t)m + o] + dv : 0.f;
             ((float*)a.F)[4 * (size_t)m + o] = val;
             ((float*)a.dF)[4 * (size_t)m + o] = val;
           }
@@ -419,6 +423,7 @@ void run_infer(iblbm_ctx* c, float* y_out) {
   a.dim = c->dim;
   a.F = c->mF;
   a.dF = c->mdF;
+  a.Fprev = c->mFprev;
   a.fp64 = c->fp64;
   a.y = y_out;
   // three waves per SIMD fit the kernel's registers: 256 CUs x 4 SIMDs x 3
@@ -490,6 +495,18 @@ __global__ void k_loss_total(const float* part, int parts, double count, float* 
 // features, MLP prediction, its spreading, one plain correction pass, the slip check and,
 // when the slip exceeds the tolerance, a full MDF redo with fallback_iters passes whose
 // kernels run only when the device flag is set.
+#define HIP_STEP(expr) hip_check(c, (expr), #expr)
+
+// The MDF fallback of the learned step: u* and the band force recomputed, then
+// fallback_iters plain passes.
+void mlp_fallback(iblbm_ctx* c) {
+  ibm_band_redo(c);  // the redo recomputes u* and clears the force at the band
+  for (int m = 0; m < c->cfg.fallback_iters; m++) {
+    ibm_interp(c, m == 0, 0);
+    ibm_spread(c, 0);
+  }
+}
+
 void mlp_step_forcing(iblbm_ctx* c) {
   tbegin(c, IBLBM_T_INTERP);
   ibm_interp(c, 1, 2);  // pass-0 slip into the features (also builds u* and the band)
@@ -501,26 +518,44 @@ void mlp_step_forcing(iblbm_ctx* c) {
   tbegin(c, IBLBM_T_SPREAD);
   ibm_spread(c, 1);
   tend(c);
+  // the correction pass; its interpolation also measures the slip the prediction left,
+  // which judges the prediction
+  tbegin(c, IBLBM_T_OTHER);
+  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, c->stream, c->dstats, 1);
+  tend(c);
   tbegin(c, IBLBM_T_INTERP);
-  ibm_interp(c, 0, 0);
+  ibm_interp(c, 0, 3);
+  tend(c);
+  tbegin(c, IBLBM_T_OTHER);
+  hipLaunchKernelGGL(k_slip_check, dim3(1), dim3(1), 0, c->stream, c->dstats, c->nmk,
+                     c->cfg.slip_tol, c->dcond, c->dstatus + 4);
+  // outside a graph the verdict goes to the host, which reads it while the correction's
+  // spreading runs and launches the fallback only when it is needed (launching its
+  // workgroups every step only to have them return costs a third of a millisecond at
+  // 256^3); inside a graph the decision stays on the device
+  const bool host_decides = !c->capturing && c->hflag;
+  if (host_decides) {
+    HIP_STEP(hipMemcpyAsync(c->hflag, c->dcond, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_STEP(hipEventRecord(c->ev_flag, c->stream));
+  }
   tend(c);
   tbegin(c, IBLBM_T_SPREAD);
   ibm_spread(c, 0);
   tend(c);
-  // slip after the correction, then the conditional fallback
-  tbegin(c, IBLBM_T_OTHER);
-  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, c->stream, c->dstats, 1);
-  ibm_interp(c, 0, 1);
-  hipLaunchKernelGGL(k_slip_check, dim3(1), dim3(1), 0, c->stream, c->dstats, c->nmk,
-                     c->cfg.slip_tol, c->dcond, c->dstatus + 4);
-  c->cond = c->dcond;
-  ibm_band_redo(c);  // the redo recomputes u* and clears the force at the band
-  for (int m = 0; m < c->cfg.fallback_iters; m++) {
-    ibm_interp(c, m == 0, 0);
-    ibm_spread(c, 0);
+  if (host_decides) {
+    HIP_STEP(hipEventSynchronize(c->ev_flag));
+    if (*c->hflag) {
+      tbegin(c, IBLBM_T_OTHER);
+      mlp_fallback(c);
+      tend(c);
+    }
+  } else {
+    tbegin(c, IBLBM_T_OTHER);
+    c->cond = c->dcond;
+    mlp_fallback(c);
+    c->cond = nullptr;
+    tend(c);
   }
-  c->cond = nullptr;
-  tend(c);
 }
 
 void mlp_features(iblbm_ctx* c) { run_features(c); }
@@ -530,12 +565,31 @@ extern "C" {
 
 iblbm_status iblbm_set_mlp(iblbm_ctx* c, const float* params, const float* norm) {
   if (!c || !params || !norm) return IBLBM_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return IBLBM_E_DEVICE;
   if (!c->mlp_w) {
-    if (hipMalloc(&c->mlp_w, NPARAM * sizeof(float)) != hipSuccess) return IBLBM_E_NOMEM;
-    if (hipMalloc(&c->mlp_norm, 32 * sizeof(float)) != hipSuccess) return IBLBM_E_NOMEM;
+    // through the context's allocator, released with the context
+    c->mlp_w = ctx_alloc(c, NPARAM * sizeof(float));
+    c->mlp_norm = c->mlp_w ? (float*)ctx_alloc(c, 32 * sizeof(float)) : nullptr;
+    if (!c->mlp_w || !c->mlp_norm) {
+      c->mlp_w = nullptr;
+      return IBLBM_E_NOMEM;
+    }
   }
-  if (hipMemcpy(c->mlp_w, params, NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->mlp_norm, norm, 26 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+  if (!c->hflag) {
+    if (hipHostMalloc((void**)&c->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      c->hflag = nullptr;
+      return IBLBM_E_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&c->ev_flag, hipEventDisableTiming) != hipSuccess) {
+      c->ev_flag = nullptr;
+      return IBLBM_E_DEVICE;
+    }
+  }
+  if (hipMemcpyAsync(c->mlp_w, params, NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->mlp_norm, norm, 26 * sizeof(float), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     c->err = "copying the MLP parameters failed";
     return IBLBM_E_DEVICE;
   }
@@ -601,6 +655,7 @@ iblbm_status iblbm_nn_forward(const float* x, int64_t n, const float* params, fl
   a.dim = 3;
   a.F = nullptr;
   a.dF = nullptr;
+  a.Fprev = nullptr;
   a.fp64 = 0;
   a.y = dY;
   int waves = (int)std::min<int64_t>((n + 15) / 16, INFER_WAVES);

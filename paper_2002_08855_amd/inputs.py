@@ -95,6 +95,8 @@ def workload(name: str) -> dict:
     cavity256_train   : the training source of the learned forcing: cavity256_f32's shape
                         (1565 spheres, 0.20, random sequential addition) with seed 103,
                         plain MDF-5.
+    cavity256_train30 : the second training source: 2347 spheres D=16 (0.30) on a
+                        10-cell FCC lattice thinned with seed 105, plain MDF-5.
     np2d_<Np> / np3d_<Np>: the particle-count series of Table 7: 2048^2 FP32 with Np
                         disks D=16 (Np <= 10^4), 150^3 FP32 with Np spheres D=12 (Np <= 600),
                         round(pi D) / round(pi D^2) points, ratio 1.5, MDF-3, on a thinned
@@ -219,6 +221,16 @@ def workload(name: str) -> dict:
         p = default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=5)
         X = rsa(seed=103, dim=3, n=(256, 256, 256), count=1565, diameter=16.0, gap=0.5,
                 clearance=2.5)
+        parts = dict(center=X, diameter=np.full(len(X), 16.0), density=np.full(len(X), 2.0),
+                     n_markers=804)
+        return dict(params=p, particles=parts, steps=200)
+    if name == "cavity256_train30":
+        # a second training packing at the evaluation's volume fraction 0.30: a finer FCC
+        # lattice (10 cells, nearest-neighbour gap about 2 lu instead of 4) thinned with
+        # its own seed, so that no training sphere sits on an evaluation site pattern
+        p = default_params(3, (256, 256, 256), tau=0.7, storage="f32", mdf_iters=5)
+        X = fcc_fill(seed=105, n=256, cells=10, diameter=16.0, count=2347, clearance=1.0,
+                     jitter=0.5)
         parts = dict(center=X, diameter=np.full(len(X), 16.0), density=np.full(len(X), 2.0),
                      n_markers=804)
         return dict(params=p, particles=parts, steps=200)

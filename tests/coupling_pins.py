@@ -268,6 +268,41 @@ def pin_gap_feature_geometry(L=None):
         assert g == 0.0, g
 
 
+# ---------------------------------------------------------------------------
+# learned forcing: the prediction's output transform
+
+def pin_learned_force_prediction(L=None):
+    """The learned force F = F_prev + target mean + target std * y, y the network's
+    output on the features normalised by their mean and std: with zero weights y is the
+    output bias; with one path through the network y0 = c tanh(b tanh(a x0)) on the
+    normalised first feature.  Components past the lattice dimension are zero."""
+    NP = oracle.NPARAM
+    rng = np.random.default_rng(5)
+    n = 9
+    feat = rng.normal(size=(n, 10))
+    Fprev = rng.normal(size=(n, 3))
+    norm = np.concatenate([rng.normal(size=10), rng.uniform(0.5, 2.0, 10),
+                           [0.1, -0.2, 0.3], [2.0, 3.0, 0.5]])
+    P = np.zeros(NP)
+    P[NP - 3:] = [0.25, -0.5, 1.5]
+    want = Fprev + norm[20:23] + norm[23:26] * np.array([0.25, -0.5, 1.5])
+    _close(oracle.mlp_predict(P, norm, feat, Fprev, dim=3, L=L), want, 1e-14, 1e-15,
+           what="output bias only")
+    F2 = oracle.mlp_predict(P, norm, feat, Fprev, dim=2, L=L)
+    _close(F2[:, :2], want[:, :2], 1e-14, 1e-15, what="2-D")
+    assert np.array_equal(F2[:, 2], np.zeros(n))
+    P = np.zeros(NP)
+    P[0] = 0.7
+    off_w2 = 10 * 64 + 64
+    P[off_w2] = -1.3
+    P[off_w2 + 64 * 64 + 64] = 2.1
+    x0 = (feat[:, 0] - norm[0]) / norm[10]
+    F = oracle.mlp_predict(P, norm, feat, Fprev, dim=3, L=L)
+    y0 = 2.1 * np.tanh(-1.3 * np.tanh(0.7 * x0))
+    _close(F[:, 0], Fprev[:, 0] + norm[20] + norm[23] * y0, 1e-13, 1e-14, what="one path")
+    _close(F[:, 1:], Fprev[:, 1:] + norm[21:23], 1e-14, 1e-15, what="the other components")
+
+
 ALL = [pin_newton_euler_constant_loads, pin_newton_euler_rigid_interior,
        pin_interior_volume_and_moment, pin_loads_closed_forms, pin_wall_force_is_mirror_pair,
-       pin_gap_feature_geometry]
+       pin_gap_feature_geometry, pin_learned_force_prediction]

@@ -91,8 +91,8 @@ def test_full_size_learned_step_parity():
     fraction 0.30): one plain MDF-5 step, then two learned steps (MLP prediction, one
     correction pass, the slip judge), GPU with BF16 MFMA inference against the FP64 oracle
     on the same BF16-rounded weights.  The weights give O(1) outputs and the output scale
-    is the converged force of this state (from the oracle's capture), so the prediction
-    carries the boundary force.  Bound: 2^-6 relative, eight BF16 unit roundoffs, as for
+    is that of the converged force's change over a step in this state (from the oracle's
+    capture), so the prediction carries the force's update.  Bound: 2^-6 relative, eight BF16 unit roundoffs, as for
     the small learned-step case."""
     b = _gpu()
     w = inputs.workload("cavity256_learned")
@@ -105,7 +105,8 @@ def test_full_size_learned_step_parity():
                         n_markers=parts["n_markers"])
         s.step(1)  # no MLP installed yet: plain MDF-5
     f, t = o.capture_samples()
-    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    r = t - f[:, 3:6]  # the network's target: the change over the previous step's force
+    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, r.mean(0), r.std(0) + 1e-12])
     P = _bf16(np.random.default_rng(11).normal(0.0, 0.3, oracle.NPARAM))
     y = oracle.mlp_forward(P, (f - norm[:10]) / norm[10:20])
     print("MLP output std", y.std(0), round(time.time() - t0, 1), "s", flush=True)

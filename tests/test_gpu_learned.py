@@ -164,8 +164,11 @@ def _collect(params, X, D, rho, steps):
 
 
 def _norm_stats(f, t):
+    """feature mean and std, then those of the network's target: the change of the
+    converged force over the previous step's (features 3..5)"""
+    r = t - f[:, 3:6]
     fm, fs = f.mean(0), f.std(0) + 1e-12
-    tm, ts = t.mean(0), t.std(0) + 1e-12
+    tm, ts = r.mean(0), r.std(0) + 1e-12
     return np.concatenate([fm, fs, tm, ts]).astype(np.float32)
 
 
@@ -186,7 +189,7 @@ def test_learned_forcing_gain_over_mdf():
     X, D, rho = _cavity(seed=23)
     norm = _norm_stats(f, t)
     xn = (f - norm[:10]) / norm[10:20]
-    tn = (t - norm[20:23]) / norm[23:26]
+    tn = (t - f[:, 3:6] - norm[20:23]) / norm[23:26]
     b = _gpu()
     P, curve = b.nn_train(xn, tn, _params(9, 0.1), epochs=40, batch=2048, lr=2e-3, seed=2)
     print("train loss", curve[0], curve[-1])
@@ -213,9 +216,9 @@ def test_learned_forcing_gain_over_mdf():
 
 
 def test_learned_step_matches_oracle():
-    """The learned step with an MLP whose outputs are O(1) and whose output scale is the
-    converged MDF-5 force of this layout, so that the prediction carries the whole
-    boundary force before the correction pass: GPU (BF16 MFMA, FP32 accumulation)
+    """The learned step with an MLP whose outputs are O(1) and whose output scale is that
+    of the converged MDF-5 force's change over a step in this layout, so that the
+    prediction carries the force's update before the correction pass: GPU (BF16 MFMA, FP32 accumulation)
     against the FP64 oracle on the same BF16-rounded weights, 5 steps.
 
     Bound: BF16 keeps 8 significant bits (unit roundoff u = 2^-9).  The inputs, the
@@ -231,7 +234,7 @@ def test_learned_step_matches_oracle():
     o0.add_particles(X, D, rho, n_markers=452)
     o0.step(5)
     f, t = o0.capture_samples()
-    norm = np.concatenate([f.mean(0), f.std(0) + 1e-12, t.mean(0), t.std(0) + 1e-12])
+    norm = _norm_stats(f, t).astype(np.float64)
     P = _bf16(_params(11, 0.3))
     y = oracle.mlp_forward(P, (f - norm[:10]) / norm[10:20])
     print("MLP output std per component", y.std(0))

@@ -2,6 +2,7 @@
 differences, and the forward pass against closed forms for special weights."""
 import numpy as np
 
+import coupling_pins as pins
 import oracle
 
 NP = oracle.NPARAM
@@ -46,3 +47,8 @@ def test_gradient_matches_finite_differences():
         Pm[i] -= h
         fd = (oracle.mlp_loss_grad(Pp, x, t)[0] - oracle.mlp_loss_grad(Pm, x, t)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+
+def test_predicted_force_is_the_previous_plus_the_scaled_change():
+    pins.pin_learned_force_prediction()

@@ -43,6 +43,17 @@ MUTATIONS = [
      "double gg = sqrt(d2) - D[o];", pins.pin_gap_feature_geometry),
     ("gap not clamped at zero", "return gap < 0.0 ? 0.0 : gap;", "return gap;",
      pins.pin_gap_feature_geometry),
+    ("learned force without the previous step's",
+     "F[3 * m + o] = o < dim ? Fprev[3 * m + o] + (tmean[o] + tsd[o] * y[NO * m + o]) : 0.0;",
+     "F[3 * m + o] = o < dim ? (tmean[o] + tsd[o] * y[NO * m + o]) : 0.0;",
+     pins.pin_learned_force_prediction),
+    ("target mean and std swapped",
+     "F[3 * m + o] = o < dim ? Fprev[3 * m + o] + (tmean[o] + tsd[o] * y[NO * m + o]) : 0.0;",
+     "F[3 * m + o] = o < dim ? Fprev[3 * m + o] + (tsd[o] + tmean[o] * y[NO * m + o]) : 0.0;",
+     pins.pin_learned_force_prediction),
+    ("features not divided by their std",
+     "xn[NI * m + i] = (feat[NI * m + i] - mean[i]) / sd[i];",
+     "xn[NI * m + i] = feat[NI * m + i] - mean[i];", pins.pin_learned_force_prediction),
 ]
 
 
