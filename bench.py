@@ -97,7 +97,7 @@ def run(args):
     torch.cuda.synchronize()
 
     # per-group kernel-time breakdown (every group bracketed by HIP events)
-    sim.set_timing(1)
+    sim.set_timing(-1)
     sim.reset_stats()
     nb = max(5, min(args.steps, 50))
     sim.step(nb)
@@ -105,12 +105,23 @@ def run(args):
     per_group = {g: (st["time_ms"][g] / nb) for g in GROUPS if st["launches"][g]}
     dominant = max(per_group, key=per_group.get)
     band_nodes = st["band_nodes"]
+    # the collide-stream kernel by itself (events with its launch), over the same steps
+    sim.set_timing(1 << GROUPS.index("collide"))
+    sim.set_timing_kernel(True)
+    sim.reset_stats()
+    sim.step(nb)
+    st_c = sim.stats()
+    sim.set_timing_kernel(False)
 
     # timed region: only the dominant group carries events (2 per launch), and only in
     # every TIMING_EVERY-th step, so that the events' own cost (an extra queue packet
     # each) stays out of the throughput
     sim.set_timing(1 << GROUPS.index(dominant))
     sim.set_timing_every(TIMING_EVERY)
+    # the collide, interpolation and spreading kernels are timed on their own, with events
+    # recorded as part of their launch (as the profiler times them)
+    kernel_only = dominant in ("collide", "interp", "spread")
+    sim.set_timing_kernel(kernel_only)
     sim.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -120,6 +131,7 @@ def run(args):
     st2 = sim.stats()
     sim.set_timing(0)
     sim.set_timing_every(1)
+    sim.set_timing_kernel(False)
     secs = t1 - t0
     mlups = N * args.steps / (1e6 * secs)
     launches = st2["launches"][dominant]
@@ -133,6 +145,8 @@ def run(args):
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                 "timed_every_nth_step": TIMING_EVERY,
+                "timing": "kernel execution (events with the launch)" if kernel_only
+                          else "the group's launches between events",
                 "algorithmic_bytes_per_launch": int(nbytes)}
         kname = PMC_KERNEL.get(dominant, dominant)
         prof = os.path.join(ROOT, "profiles", f"{kname}_{args.workload}_pmc.json")
@@ -140,11 +154,11 @@ def run(args):
             d = json.load(open(prof))
             if d.get("source_sha") == traffic.source_sha(kname):
                 roof["traffic"] = d.get("traffic_bytes_per_launch")
-    # the collide-stream kernel against the HBM roofline, from the breakdown pass
+    # the collide-stream kernel against the HBM roofline
     roof_collide = None
-    if "collide" in per_group:
+    if st_c["launches"]["collide"]:
         nb_c = algorithmic_bytes("collide", p, nmk, band_nodes)
-        ms_c = st["time_ms"]["collide"] / max(1, st["launches"]["collide"])
+        ms_c = st_c["time_ms"]["collide"] / st_c["launches"]["collide"]
         ach_c = nb_c / (ms_c * 1e-3) / 1e9
         roof_collide = {"kernel": "k_collide_stream", "bound": "hbm", "achieved": round(ach_c, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_c / HBM_PEAK_GBS, 4),
@@ -239,7 +253,7 @@ def _sim(binding, p, parts):
 def _breakdown(sim, steps=10):
     """kernel-group times per step (every group bracketed by HIP events)"""
     sim.set_stats_every(0)
-    sim.set_timing(1)
+    sim.set_timing(-1)
     sim.reset_stats()
     sim.step(steps)
     st = sim.stats()
@@ -434,7 +448,7 @@ def run_np_sweep(args, kind="np", suffix=""):
             steps = 100 if dim == 2 else 50
             r = _timed(sim, N, steps, 5)
             sim.set_stats_every(0)
-            sim.set_timing(1)
+            sim.set_timing(-1)
             sim.reset_stats()
             sim.step(20)
             st = sim.stats()

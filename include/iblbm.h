@@ -172,9 +172,10 @@ iblbm_status iblbm_get_pairs(iblbm_ctx* ctx, int32_t* ij, int64_t cap, int64_t* 
 iblbm_status iblbm_get_cells(iblbm_ctx* ctx, int32_t* cell, int32_t* dims);
 iblbm_status iblbm_get_stats(iblbm_ctx* ctx, iblbm_stats* out);
 iblbm_status iblbm_num_particles(iblbm_ctx* ctx, int32_t* np, int32_t* n_markers);
-/* HIP-event timing on the library's stream: 0 = off, 1 = every kernel group, otherwise
- * a bit mask over iblbm_timer groups (bit g times group g).  Events bracket each
- * launch of a timed group; the elapsed times accumulate into iblbm_stats. */
+/* HIP-event timing on the library's stream: 0 = off, -1 = every kernel group, otherwise
+ * a bit mask over iblbm_timer groups (bit g times group g, so 1 is the collide group
+ * alone).  Events bracket each launch of a timed group; the elapsed times accumulate
+ * into iblbm_stats. */
 iblbm_status iblbm_set_timing(iblbm_ctx* ctx, int32_t mask);
 iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
 #define IBLBM_OPT_IBM_LDS 1 /* 1 (default): per-particle LDS interpolation/spreading kernels;
@@ -187,6 +188,11 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
 #define IBLBM_OPT_TIMING_EVERY 4 /* >= 1 (default 1): with timing on, only the launches of
                                     steps whose index is a multiple of the value carry
                                     events, so that the events' own cost stays small */
+#define IBLBM_OPT_TIMING_KERNEL 5 /* 1: the events of the collide, interpolation and
+                                     spreading groups time the group's kernel itself
+                                     (recorded with its launch, as a profiler does); 0
+                                     (default): they bracket the group's launches,
+                                     dispatch latency included */
 iblbm_status iblbm_set_option(iblbm_ctx* ctx, int32_t option, int32_t value);
 /* Work units of the per-particle interpolation and spreading kernels for one particle:
  * host-side planning only, no device call; iblbm_add_particles applies the same plan to

@@ -299,8 +299,9 @@ class Sim:
         d["launches"] = dict(zip(TIMERS, list(s.launches)))
         return d
 
-    def set_timing(self, mask=1):
-        """0 off, 1 all kernel groups, else a bit mask over TIMERS."""
+    def set_timing(self, mask=-1):
+        """-1 (default) every kernel group, 0 off, else a bit mask over TIMERS (bit g for
+        TIMERS[g])."""
         self._check(lib().iblbm_set_timing(self.h, int(mask)))
 
     def reset_stats(self):
@@ -323,6 +324,11 @@ class Sim:
     def set_timing_every(self, k):
         """with timing on, time the launches of every k-th step only"""
         self.set_option(4, int(k))
+
+    def set_timing_kernel(self, on=True):
+        """collide, interpolation and spreading groups: time the kernel itself (events
+        recorded with its launch) instead of bracketing the group's launches"""
+        self.set_option(5, int(on))
 
     def set_graph(self, on=True):
         self._check(lib().iblbm_set_graph(self.h, int(on)))

@@ -191,6 +191,7 @@ struct iblbm_ctx {
   bool timing = false;
   int timing_mask = 0;  // bit g: time kernel group g
   int timing_every = 1; // time the launches of every timing_every-th step only
+  bool timing_kernel = false;  // collide, interp, spread: events with the kernel launch
   bool t_open = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_group;
@@ -254,6 +255,9 @@ void mlp_infer(iblbm_ctx* c);
 
 // timing helpers (host.hip)
 void tbegin(iblbm_ctx* c, int group);
+// with kernel-only timing of `group` due in this step: a start and a stop event for the
+// group's kernel launch (hipExtLaunchKernelGGL); false otherwise
+bool kernel_events(iblbm_ctx* c, int group, hipEvent_t* start, hipEvent_t* stop);
 // a failed HIP call inside a step: records the error on the context and unwinds the
 // step (to the entry point, which returns IBLBM_E_DEVICE)
 void hip_check(iblbm_ctx* c, hipError_t e, const char* expr);

@@ -421,10 +421,17 @@ int read_device_int(iblbm_ctx* c, const int* d) {
   return v;
 }
 
-void tbegin(iblbm_ctx* c, int group) {
-  c->t_open = false;
-  if (!c->timing || !((c->timing_mask >> group) & 1) || c->step % c->timing_every != 0) return;
-  c->t_open = true;
+namespace {
+
+bool timed_now(const iblbm_ctx* c, int group) {
+  return c->timing && ((c->timing_mask >> group) & 1) && c->step % c->timing_every == 0;
+}
+
+bool kernel_timed_group(int group) {
+  return group == IBLBM_T_COLLIDE || group == IBLBM_T_INTERP || group == IBLBM_T_SPREAD;
+}
+
+void reserve_events(iblbm_ctx* c) {
   if (c->ev_used + 2 > c->ev.size()) {
     for (int k = 0; k < 64; k++) {
       hipEvent_t e;
@@ -433,9 +440,30 @@ void tbegin(iblbm_ctx* c, int group) {
       c->ev_group.push_back(0);
     }
   }
+}
+
+}  // namespace
+
+void tbegin(iblbm_ctx* c, int group) {
+  c->t_open = false;
+  if (!timed_now(c, group)) return;
+  if (c->timing_kernel && kernel_timed_group(group)) return;  // the launch records them
+  c->t_open = true;
+  reserve_events(c);
   c->ev_group[c->ev_used] = group;
   HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
   c->ev_used++;
+}
+
+bool kernel_events(iblbm_ctx* c, int group, hipEvent_t* start, hipEvent_t* stop) {
+  if (!c->timing_kernel || !kernel_timed_group(group) || !timed_now(c, group)) return false;
+  reserve_events(c);
+  c->ev_group[c->ev_used] = group;
+  c->ev_group[c->ev_used + 1] = -1;
+  *start = c->ev[c->ev_used];
+  *stop = c->ev[c->ev_used + 1];
+  c->ev_used += 2;
+  return true;
 }
 
 void tend(iblbm_ctx* c) {
@@ -944,7 +972,7 @@ iblbm_status iblbm_num_particles(iblbm_ctx* c, int32_t* np, int32_t* nmk) {
 iblbm_status iblbm_set_timing(iblbm_ctx* c, int32_t mask) {
   if (!c) return IBLBM_E_ARG;
   c->timing = mask != 0;
-  c->timing_mask = mask == 1 ? 0xff : mask;
+  c->timing_mask = mask == -1 ? 0xff : mask;
   return IBLBM_OK;
 }
 
@@ -968,6 +996,11 @@ iblbm_status iblbm_set_option(iblbm_ctx* c, int32_t option, int32_t value) {
   if (option == IBLBM_OPT_BAND_PASS) {
     c->band_pass = value != 0 ? 1 : 0;
     c->graph_dirty = true;
+    return IBLBM_OK;
+  }
+  if (option == IBLBM_OPT_TIMING_KERNEL) {
+    if (value != 0 && value != 1) return fail(c, IBLBM_E_ARG, "timing_kernel must be 0 or 1");
+    c->timing_kernel = value == 1;
     return IBLBM_OK;
   }
   if (option == IBLBM_OPT_TIMING_EVERY) {

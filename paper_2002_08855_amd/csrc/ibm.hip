@@ -22,6 +22,8 @@
 #include <mutex>
 #include <set>
 
+#include <hip/hip_ext.h>
+
 #include "index_math.h"
 #include "pdf_access.h"
 
@@ -1008,7 +1010,12 @@ struct RunInterp {
     if (!FIRST) bytes = ((size_t)DIM * c->box_cap * sizeof(C) + 7) & ~(size_t)7;
     auto k = k_interp_lds<DIM, T, PAR, FIRST>;
     raise_lds_limit((const void*)k, c->lds_max - (int)INTERP_STATIC_LDS);
-    hipLaunchKernelGGL(k, dim3(c->npatch), dim3(interp_threads(c)), bytes, c->stream, a);
+    hipEvent_t t0, t1;
+    if (kernel_events(c, IBLBM_T_INTERP, &t0, &t1))
+      hipExtLaunchKernelGGL(k, dim3(c->npatch), dim3(interp_threads(c)), (uint32_t)bytes, c->stream,
+                            t0, t1, 0, a);
+    else
+      hipLaunchKernelGGL(k, dim3(c->npatch), dim3(interp_threads(c)), bytes, c->stream, a);
     if (a.mode == 1 || a.mode == 3)
       hipLaunchKernelGGL(k_sum_units, dim3(1), dim3(256), 0, c->stream, c->slip_part, c->npatch,
                          c->dstats);
@@ -1044,7 +1051,12 @@ struct RunSpread {
     auto a = make_lds_args<T>(c, 0, 0);
     auto k = k_spread_lds<DIM, C>;
     raise_lds_limit((const void*)k, c->lds_max);
-    hipLaunchKernelGGL(k, dim3(c->npatch), dim3(lds_threads(c)), bytes, c->stream, a);
+    hipEvent_t t0, t1;
+    if (kernel_events(c, IBLBM_T_SPREAD, &t0, &t1))
+      hipExtLaunchKernelGGL(k, dim3(c->npatch), dim3(lds_threads(c)), (uint32_t)bytes, c->stream,
+                            t0, t1, 0, a);
+    else
+      hipLaunchKernelGGL(k, dim3(c->npatch), dim3(lds_threads(c)), bytes, c->stream, a);
     *done = true;
   }
 };

@@ -8,6 +8,8 @@
 // each thread reads and writes the same set of locations and the update is in place
 // and race free.  Links that leave through a wall bounce back half-way with the
 // moving-wall term 2 w_a rho0 (e_a . u_w)/c_s^2.
+#include <hip/hip_ext.h>
+
 #include "index_math.h"
 #include "pdf_access.h"
 
@@ -350,10 +352,12 @@ struct RunCollide {
     a.nbx = (c->cfg.n[0] + BX - 1) / BX;
     a.nblk = a.nbx * c->cfg.n[1] * c->cfg.n[2];
     a.xcd_per = (a.nblk % 8 == 0) ? a.nblk / 8 : 0;
-    if (c->parity == 0)
-      hipLaunchKernelGGL((k_collide_stream<DIM, T, 0, BX>), dim3(a.nblk), dim3(BX), 0, c->stream, a);
+    auto k = c->parity == 0 ? k_collide_stream<DIM, T, 0, BX> : k_collide_stream<DIM, T, 1, BX>;
+    hipEvent_t t0, t1;
+    if (kernel_events(c, IBLBM_T_COLLIDE, &t0, &t1))
+      hipExtLaunchKernelGGL(k, dim3(a.nblk), dim3(BX), 0, c->stream, t0, t1, 0, a);
     else
-      hipLaunchKernelGGL((k_collide_stream<DIM, T, 1, BX>), dim3(a.nblk), dim3(BX), 0, c->stream, a);
+      hipLaunchKernelGGL(k, dim3(a.nblk), dim3(BX), 0, c->stream, a);
   }
   static void run(iblbm_ctx* c) {
     using C = typename Store<T>::C;
