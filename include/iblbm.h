@@ -249,7 +249,7 @@ iblbm_status iblbm_nn_grad(const float* x, const float* t, int64_t n, const floa
  * synchronising.  x (n*10), t (n*3) and params (5059) are device inputs; loss (1 float)
  * and grad (5059) are device outputs, written by the same kernels as iblbm_nn_grad (the
  * loss as the FP64 sum of the same per-block partials).  The activations live in a fixed
- * scratch array of 8.6 MB that the library holds on each device until the process
+ * scratch array of 9.1 MB that the library holds on each device until the process
  * ends: n may not exceed IBLBM_NOALLOC_MAX_SAMPLES (IBLBM_E_CAPACITY), and no
  * allocation or free happens in the call.  Calls that overlap on one device share that
  * scratch and race: serialise them (one stream, or events).  IBLBM_E_ARG for NULL

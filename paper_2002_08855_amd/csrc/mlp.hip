@@ -9,7 +9,8 @@
 // next layer needs and no data moves between layers.  One wavefront walks 16-point tiles
 // with all weights held in registers.
 //
-// Training uses the same library: FP32 GEMMs through LDS tiles, fused elementwise
+// Training uses the same library: FP32 GEMMs through LDS tiles (the weight gradients with
+// the batch split over blocks and the partials added in a fixed order), fused elementwise
 // kernels and Adam, all on the GPU.
 #include <math.h>
 #include <string.h>
@@ -268,6 +269,37 @@ __global__ void k_gemm(const float* A, const float* B, float* Cm, int M, int N, 
   if (row < M && col < N) Cm[(size_t)row * N + col] = acc ? Cm[(size_t)row * N + col] + s : s;
 }
 
+// Weight gradients C[M x N] = A^T B with A stored K x M and B stored K x N, K the batch:
+// the K range is split over SPLITK blocks per 16x16 output tile (one tile per block would
+// leave the chip idle on a 64 x 64 output), each block writing its partial tile; the
+// partials are then added in split order, so the result does not depend on scheduling.
+constexpr int SPLITK = 32;
+__global__ void k_gemm_tn_split(const float* A, const float* B, float* part, int M, int N, int K) {
+  __shared__ float As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16, z = blockIdx.z;
+  const int per = (K + SPLITK - 1) / SPLITK, klo = z * per, khi = min(K, klo + per);
+  float s = 0.f;
+  for (int k0 = klo; k0 < khi; k0 += 16) {
+    const int k = k0 + ty;  // one K row per thread row: coalesced along tx
+    As[ty][tx] = (k < khi && m0 + tx < M) ? A[(size_t)k * M + m0 + tx] : 0.f;
+    Bs[ty][tx] = (k < khi && n0 + tx < N) ? B[(size_t)k * N + n0 + tx] : 0.f;
+    __syncthreads();
+    for (int kk = 0; kk < 16; kk++) s += As[kk][ty] * Bs[kk][tx];
+    __syncthreads();
+  }
+  const int row = m0 + ty, col = n0 + tx;
+  if (row < M && col < N) part[((size_t)z * M + row) * N + col] = s;
+}
+
+__global__ void k_sum_splits(const float* part, float* C, int M, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  float s = 0.f;
+  for (int z = 0; z < SPLITK; z++) s += part[(size_t)z * M * N + i];
+  C[i] = s;
+}
+
 // Z[M x N] += bias[N]; H = tanh(Z) (act) or H = Z
 __global__ void k_bias_act(float* Z, const float* bias, int M, int N, int act) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,6 +372,7 @@ struct Net {
   float *Z1, *Z2, *Y, *dY; // activations (B x 64, B x 64, B x 3)
   float *dH1, *dH2;
   float* loss_part;
+  float* part;  // SPLITK x 64 x 64 partial weight gradients
   int B;
 };
 
@@ -347,6 +380,14 @@ void gemm(hipStream_t s, const float* A, const float* B, float* C, int M, int N,
           int acc = 0) {
   dim3 grid((N + 15) / 16, (M + 15) / 16);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, A, B, C, M, N, K, tA, tB, acc);
+}
+
+// weight gradient C = A^T B over the batch (A: K x M, B: K x N; M, N <= 64)
+void gemm_wgrad(hipStream_t s, const float* A, const float* B, float* C, int M, int N, int K,
+                float* part) {
+  dim3 grid((N + 15) / 16, (M + 15) / 16, SPLITK);
+  hipLaunchKernelGGL(k_gemm_tn_split, grid, dim3(256), 0, s, A, B, part, M, N, K);
+  hipLaunchKernelGGL(k_sum_splits, dim3((M * N + 255) / 256), dim3(256), 0, s, part, C, M, N);
 }
 
 // forward and backward of the MSE loss on a batch X (B x 10), T (B x 3); grads into n.G
@@ -363,15 +404,15 @@ void fwd_bwd(hipStream_t s, Net& n, const float* X, const float* T, int B) {
   hipLaunchKernelGGL(k_bias_act, blocks((size_t)B * NO), dim3(256), 0, s, n.Y, P + OFF_B3, B, NO, 0);
   hipLaunchKernelGGL(k_mse, blocks((size_t)B * NO), dim3(256), 0, s, n.Y, T, n.dY, B, NO, n.loss_part);
   // backward
-  gemm(s, n.dY, n.Z2, G + OFF_W3, NO, NH, B, 1, 0);  // dW3 = dY^T H2
+  gemm_wgrad(s, n.dY, n.Z2, G + OFF_W3, NO, NH, B, n.part);  // dW3 = dY^T H2
   hipLaunchKernelGGL(k_colsum, dim3(NO), dim3(256), 0, s, n.dY, G + OFF_B3, B, NO);
   gemm(s, n.dY, P + OFF_W3, n.dH2, B, NH, NO, 0, 0);  // dH2 = dY W3
   hipLaunchKernelGGL(k_tanh_back, blocks((size_t)B * NH), dim3(256), 0, s, n.dH2, n.Z2, (size_t)B * NH);
-  gemm(s, n.dH2, n.Z1, G + OFF_W2, NH, NH, B, 1, 0);  // dW2 = dZ2^T H1
+  gemm_wgrad(s, n.dH2, n.Z1, G + OFF_W2, NH, NH, B, n.part);  // dW2 = dZ2^T H1
   hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dH2, G + OFF_B2, B, NH);
   gemm(s, n.dH2, P + OFF_W2, n.dH1, B, NH, NH, 0, 0);  // dH1 = dZ2 W2
   hipLaunchKernelGGL(k_tanh_back, blocks((size_t)B * NH), dim3(256), 0, s, n.dH1, n.Z1, (size_t)B * NH);
-  gemm(s, n.dH1, X, G + OFF_W1, NH, NI, B, 1, 0);  // dW1 = dZ1^T X
+  gemm_wgrad(s, n.dH1, X, G + OFF_W1, NH, NI, B, n.part);  // dW1 = dZ1^T X
   hipLaunchKernelGGL(k_colsum, dim3(NH), dim3(256), 0, s, n.dH1, G + OFF_B1, B, NH);
 }
 
@@ -401,6 +442,7 @@ Net make_net(DevBuf& db, int B) {
   n.dH1 = db.get<float>((size_t)B * NH);
   n.dH2 = db.get<float>((size_t)B * NH);
   n.loss_part = db.get<float>(((size_t)B * NO + 255) / 256);
+  n.part = db.get<float>((size_t)SPLITK * NH * NH);
   return n;
 }
 
@@ -452,14 +494,15 @@ void run_features(iblbm_ctx* c) {
 // ---------------------------------------------------------------------------
 // Fixed device scratch of the allocation-free gradient entry point: the activations
 // Z1, Z2 (tanh outputs), dH1, dH2 (n x 64 each), Y, dY (n x 3) and the per-block partial
-// losses of up to NOALLOC_MAX samples, 8.6 MB.  Each device holds its own copy for the
+// losses of up to NOALLOC_MAX samples, and the split partial weight gradients, 9.1 MB.
+// Each device holds its own copy for the
 // life of the process.  In host code `scratch` is only a stand-in symbol: its device
 // address comes from hipGetSymbolAddress, once per device, and only that address is
 // handed to kernels.
 constexpr int NOALLOC_MAX = 8192;
 constexpr size_t NOALLOC_PARTS = ((size_t)NOALLOC_MAX * NO + 255) / 256;
-constexpr size_t NOALLOC_FLOATS =
-    4 * (size_t)NOALLOC_MAX * NH + 2 * (size_t)NOALLOC_MAX * NO + ((NOALLOC_PARTS + 63) & ~(size_t)63);
+constexpr size_t NOALLOC_FLOATS = 4 * (size_t)NOALLOC_MAX * NH + 2 * (size_t)NOALLOC_MAX * NO +
+                                  ((NOALLOC_PARTS + 63) & ~(size_t)63) + (size_t)SPLITK * NH * NH;
 __device__ __align__(256) float scratch[NOALLOC_FLOATS];
 
 constexpr int MAX_DEVICES = 64;
@@ -711,6 +754,8 @@ iblbm_status iblbm_nn_grad_noalloc(const float* x, const float* t, int64_t n, co
   net.dY = q;
   q += (size_t)B * NO;
   net.loss_part = q;
+  q += (NOALLOC_PARTS + 63) & ~(size_t)63;
+  net.part = q;
   hipStream_t s = (hipStream_t)stream;
   fwd_bwd(s, net, x, t, B);
   const int parts = (B * NO + 255) / 256;
