@@ -58,3 +58,39 @@ def test_graph_replay_matches_plain_launches(dim):
     eager.step(3)
     graph.step(3)
     assert rel_l2(graph.fields()[1], eager.fields()[1]) < 1e-12
+
+
+@pytest.mark.parametrize("slip_tol,falls_back", [(1e30, False), (0.0, True)])
+def test_graph_replay_learned_forcing(slip_tol, falls_back):
+    """The learned step (BF16 MFMA prediction, correction pass, slip judge) replayed from
+    graphs, where the fallback decision stays on the device, against plain launches, where
+    the host reads the verdict: with a tolerance every prediction meets (no fallback) and
+    with one none meets (MDF fallback on every step).  FP64 storage."""
+    b = _gpu()
+    p = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f64", mdf_iters=5, forcing=1,
+                              slip_tol=slip_tol, fallback_iters=3)
+    X = inputs.jittered_grid(seed=25, nx=2, ny=2, pitch=20.0, origin=12.0, jitter=1.0, nz=2)
+    P = np.random.default_rng(11).normal(0.0, 0.3, b.NPARAM)
+    norm = np.concatenate([np.zeros(10), np.full(10, 1e-5), np.zeros(3), np.full(3, 1e-6)])
+    sims = []
+    for use_graph in (False, True):
+        s = b.Sim(p)
+        s.add_particles(X, np.full(len(X), 12.0), np.full(len(X), 2.0), n_markers=452)
+        s.set_mlp(P, norm)
+        s.set_graph(use_graph)
+        sims.append(s)
+    eager, graph = sims
+    total = 0
+    for n in (1, 2, 3, 1):
+        eager.step(n)
+        graph.step(n)
+        total += n
+        pe, ue, fe = eager.fields()
+        pg, ug, fg = graph.fields()
+        e = [rel_l2(pg, pe), rel_l2(ug, ue), rel_l2(fg, fe),
+             rel_l2(graph.particles()["U"], eager.particles()["U"])]
+        print(slip_tol, n, e, flush=True)
+        assert max(e) < 1e-12, e
+    assert np.linalg.norm(ue) > 0
+    fe_, fg_ = eager.stats()["fallbacks"], graph.stats()["fallbacks"]
+    assert fe_ == fg_ == (total if falls_back else 0), (fe_, fg_)
