@@ -43,16 +43,15 @@ def progress(msg):
 
 
 def algorithmic_bytes(group, p, nmk, band_nodes):
-    """Bytes one launch of a kernel group must move, as the survey's measurement section
-    defines them (f_0, padding and the method's own bookkeeping not credited):
+    """Bytes one launch of a kernel group must move (f_0, padding and the method's own
+    bookkeeping not credited):
       collide-stream   2 (q-1) s per node + d cs per band node (the force read)
       band u*          ((q-1) s + d cs) per band node
       interp + spread  per forcing pass 2 d cs per band node + 16 d per point (offsets in
                        FP64, U_b and dF); split as interpolation d cs per band node +
                        12 d per point (u read; offsets, U_b) and spreading d cs per band
                        node + 4 d per point (f update; dF)
-    with s the stored PDF size and cs the compute size (4 in FP32 as the survey states,
-    8 in FP64).  In 2-D the band u* is made inside the first of the mdf_iters
+    with s the stored PDF size and cs the compute size (4, and 8 in FP64).  In 2-D the band u* is made inside the first of the mdf_iters
     interpolation launches, so each interpolation launch carries 1/mdf_iters of it."""
     dim = p["dim"]
     q = 9 if dim == 2 else 19
@@ -201,9 +200,9 @@ def run(args):
 
 
 def slip_run(binding, w, steps, params=None, mlp=None):
-    """The slip error as the survey's measurement section defines it: the rms of
-    |U_b - D_I u| over the points after the step's final forcing pass, averaged over the
-    last half of a run of `steps` steps from the workload's initial state."""
+    """The slip error: the rms of |U_b - D_I u| over the points after the step's final
+    forcing pass, averaged over the last half of a run of `steps` steps from the
+    workload's initial state."""
     import numpy as np
 
     p = dict(params if params is not None else w["params"])
