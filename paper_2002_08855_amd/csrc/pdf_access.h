@@ -173,8 +173,11 @@ __device__ __forceinline__ void load_odd_interior(T* const* slot, int i, int sy,
   using L = Lat<DIM>;
   if constexpr (A < L::Q) {
     constexpr int O = opp_dir(A, L::H);
+    // 3-D directions without an x component read a whole row that no other wavefront
+    // touches: non-temporal; those with one share lines across wavefronts: cached
+    constexpr bool NT = DIM == 3 && L::ex[A] == 0;
     f[A] = Store<T>::load(
-        ld_pdf<false>(&slot[O - 1][i - (L::ex[A] + sy * L::ey[A] + sz * L::ez[A])]), inv_s);
+        ld_pdf<NT>(&slot[O - 1][i - (L::ex[A] + sy * L::ey[A] + sz * L::ez[A])]), inv_s);
     load_odd_interior<DIM, T, A + 1>(slot, i, sy, sz, inv_s, f);
   }
 }
@@ -185,8 +188,9 @@ __device__ __forceinline__ void store_odd_interior(T* const* slot, int i, int sy
                                                    const typename Store<T>::C* f) {
   using L = Lat<DIM>;
   if constexpr (A < L::Q) {
-    st_pdf<false>(&slot[A - 1][i + (L::ex[A] + sy * L::ey[A] + sz * L::ez[A])],
-                          Store<T>::save(f[A], inv_s));
+    constexpr bool NT = DIM == 3 && L::ex[A] == 0;
+    st_pdf<NT>(&slot[A - 1][i + (L::ex[A] + sy * L::ey[A] + sz * L::ez[A])],
+               Store<T>::save(f[A], inv_s));
     store_odd_interior<DIM, T, A + 1>(slot, i, sy, sz, inv_s, f);
   }
 }
