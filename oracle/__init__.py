@@ -94,6 +94,7 @@ def load(path):
             "ref_slip_rms": (C.c_double, [C.c_void_p]),
             "ref_truncated": (C.c_int64, [C.c_void_p]),
             "ref_fallbacks": (C.c_int32, [C.c_void_p]),
+            "ref_judged_slip": (C.c_double, [C.c_void_p]),
             "ref_mlp_forward": (None, [_d, C.c_int64, _d, _d]),
             "ref_mlp_predict": (None, [_d, _d, C.c_int64, C.c_int32, _d, _d, _d]),
             "ref_mlp_loss_grad": (C.c_double, [_d, C.c_int64, _d, _d, _d]),
@@ -451,6 +452,10 @@ class Sim:
 
     def fallbacks(self):
         return lib().ref_fallbacks(self.h)
+
+    def judged_slip(self):
+        """the slip the last learned prediction left, which the fallback tolerance judges"""
+        return lib().ref_judged_slip(self.h)
 
     def set_mlp(self, params, norm):
         lib().ref_set_mlp(self.h, _dp(_f64(params)), _dp(_f64(norm)))

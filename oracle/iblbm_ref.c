@@ -374,6 +374,7 @@ struct ref_ctx {
   int64_t npairs, cappairs;
   long truncated;
   double slip;
+  double judged;  /* the slip the last learned prediction left (its judge) */
   /* learned forcing */
   int has_mlp;
   double mlp[REF_MLP_NPARAM];
@@ -769,6 +770,7 @@ static void ibm_stage(ref_ctx* c) {
     forcing_pass(c, Fp);
     /* the judge: the slip the prediction leaves, which the correction pass then corrects */
     double judged = slip_rms(c);
+    c->judged = judged;
     forcing_pass(c, NULL);
     c->slip = slip_rms(c);
     if (!(judged <= c->cfg.slip_tol)) {
@@ -1236,6 +1238,7 @@ double ref_mass(const ref_ctx* c) {
 double ref_slip_rms(const ref_ctx* c) { return c->slip; }
 int64_t ref_truncated(const ref_ctx* c) { return c->truncated; }
 int32_t ref_fallbacks(const ref_ctx* c) { return c->fallbacks; }
+double ref_judged_slip(const ref_ctx* c) { return c->judged; }
 
 /* ------------------------------------------------------------------------ */
 /* learned forcing: MLP 10 -> 64 -> 64 -> 3 with tanh hidden layers          */

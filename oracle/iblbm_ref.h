@@ -132,6 +132,9 @@ double ref_mass(const ref_ctx* c);
 double ref_slip_rms(const ref_ctx* c);
 int64_t ref_truncated(const ref_ctx* c);
 int32_t ref_fallbacks(const ref_ctx* c);
+/* the rms slip the last learned prediction left before its correction pass: the value the
+ * fallback tolerance is tested against (0 before any learned step) */
+double ref_judged_slip(const ref_ctx* c);
 
 /* ---- learned forcing (MLP 10-64-64-3, tanh) --------------------------- */
 #define REF_MLP_IN 10

@@ -284,3 +284,42 @@ def test_fallback_engages_on_tight_tolerance():
     _, u1, f1 = g1.fields()
     _, u2, f2 = g2.fields()
     assert np.linalg.norm(u1 - u2) / np.linalg.norm(u2) < 1e-12
+
+
+def test_fallback_judge_is_the_slip_the_prediction_leaves():
+    """The fallback tolerance judges the slip the prediction leaves (measured by the
+    correction pass before it spreads), not the smaller slip after the correction: with a
+    tolerance between the two, which the oracle reports for the step, both sides fall back
+    on that step and then agree to FP64 rounding (the fallback's MDF passes replace the
+    prediction); with a tolerance above both, neither falls back."""
+    X, D, rho = _cavity(seed=25)
+    p = inputs.default_params(3, (44, 44, 44), tau=0.7, storage="f64", mdf_iters=5,
+                              fallback_iters=3)
+    o0 = oracle.Sim(p)
+    o0.add_particles(X, D, rho, n_markers=452)
+    o0.step(5)
+    f, t = o0.capture_samples()
+    norm = _norm_stats(f, t).astype(np.float64)
+    P = _bf16(_params(11, 0.3))
+
+    def run(side, tol):
+        s = (_gpu().Sim if side == "gpu" else oracle.Sim)(dict(p, forcing=1, slip_tol=tol))
+        s.add_particles(X, D, rho, n_markers=452)
+        s.step(5)  # no MLP installed yet: plain MDF-5
+        s.set_mlp(P, norm)
+        s.step(1)
+        return s
+
+    probe = run("oracle", 1e30)
+    judged, after = probe.judged_slip(), probe.slip_rms()
+    print("judged", judged, "after the correction", after)
+    # the tolerance sits about 20% from either value, far beyond the BF16 prediction's
+    # effect on the judged slip
+    assert judged > 1.4 * after > 0.0
+    tol = (judged * after) ** 0.5
+    g, o = run("gpu", tol), run("oracle", tol)
+    assert o.fallbacks() == 1 and g.stats()["fallbacks"] == 1
+    for a_, r_ in zip(g.fields(), o.fields()):
+        assert np.linalg.norm(a_ - r_) / np.linalg.norm(r_) < 1e-11
+    g, o = run("gpu", 2.0 * judged), run("oracle", 2.0 * judged)
+    assert o.fallbacks() == 0 and g.stats()["fallbacks"] == 0
