@@ -261,8 +261,6 @@ bool kernel_events(iblbm_ctx* c, int group, hipEvent_t* start, hipEvent_t* stop)
 // a failed HIP call inside a step: records the error on the context and unwinds the
 // step (to the entry point, which returns IBLBM_E_DEVICE)
 void hip_check(iblbm_ctx* c, hipError_t e, const char* expr);
-// one int from device memory, read on the context's stream (waits for the stream)
-int read_device_int(iblbm_ctx* c, const int* d);
 // device memory through the caller's allocator callbacks when given (else hipMalloc),
 // released with the context; nullptr (and the context's error set) on failure
 void* ctx_alloc(iblbm_ctx* c, size_t bytes);

@@ -414,13 +414,6 @@ void* ctx_alloc(iblbm_ctx* c, size_t bytes) {
   }
 }
 
-int read_device_int(iblbm_ctx* c, const int* d) {
-  int v = 0;
-  HIPCHK(hipMemcpyAsync(&v, d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return v;
-}
-
 namespace {
 
 bool timed_now(const iblbm_ctx* c, int group) {

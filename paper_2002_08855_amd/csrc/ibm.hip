@@ -578,13 +578,16 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
         b.at(t[u], x, y, z);
         const size_t i = (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
         us[u] = load_node<DIM>(a.ustar, i);
-        fa[u] = load_node<DIM>(a.facc, i);
+        // the step's first pass finds the force cleared at every listed node: not read
+        if (!a.first_pass) fa[u] = load_node<DIM>(a.facc, i);
       }
 #pragma unroll
       for (int u = 0; u < LIST_BATCH; u++) {
         if (t[u] < 0) continue;
 #pragma unroll
-        for (int c = 0; c < DIM; c++) ub[c * a.cap + t[u]] = comp<C>(us[u], c) + comp<C>(fa[u], c) * a.half_inv_rho;
+        for (int c = 0; c < DIM; c++)
+          ub[c * a.cap + t[u]] = a.first_pass ? comp<C>(us[u], c)
+                                              : comp<C>(us[u], c) + comp<C>(fa[u], c) * a.half_inv_rho;
       }
     }
   }
