@@ -752,7 +752,38 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
   int e = bound > 0.0 ? FX::BITS - 1 - ilogb(bound) : 0;
   e = e > FX::EMAX ? FX::EMAX : e;
   const C scale = C(ldexp(1.0, e)), inv = C(ldexp(1.0, -e));
-  if (has) {
+  // a point whose whole support lies inside the lattice and the box (all but those next
+  // to a wall) adds without per-node tests; scaling by 2^e is exact, so F scale ww equals
+  // the F ww scale of the general loop bit for bit
+  bool whole = has;
+#pragma unroll
+  for (int ax = 0; ax < 3; ax++) {
+    const int wd = ax < DIM ? width : 1;
+    whole = whole && g0[ax] >= 0 && g0[ax] + wd <= a.g.n[ax] && g0[ax] >= b.lo[ax] &&
+            g0[ax] + wd <= b.lo[ax] + b.B[ax];
+  }
+  if (whole) {
+    C Fs[3];
+#pragma unroll
+    for (int c = 0; c < DIM; c++) Fs[c] = F[c] * scale;
+    const int t0 = (g0[0] - b.lo[0]) + b.B[0] * ((g0[1] - b.lo[1]) + b.B[1] * (g0[2] - b.lo[2]));
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 4 : 1); iz++)
+#pragma unroll
+      for (int iy = 0; iy < 4; iy++) {
+        if ((DIM == 3 && iz >= width) || iy >= width) continue;
+        const int trow = t0 + b.B[0] * (iy + b.B[1] * iz);
+        const C wyz = DIM == 3 ? w[1][iy] : C(1);
+#pragma unroll
+        for (int ix = 0; ix < 4; ix++) {
+          if (ix >= width) continue;
+          // (phi_x phi_y) phi_z, the product order of Eq. 12
+          const C ww = DIM == 3 ? (w[0][ix] * wyz) * w[2][iz] : w[0][ix] * w[1][iy];
+#pragma unroll
+          for (int c = 0; c < DIM; c++) atomicAdd(&acc[c * a.cap + trow + ix], FX::quant(Fs[c] * ww));
+        }
+      }
+  } else if (has) {
 #pragma unroll
     for (int iz = 0; iz < (DIM == 3 ? 4 : 1); iz++)
 #pragma unroll
