@@ -182,8 +182,10 @@ iblbm_status iblbm_reset_stats(iblbm_ctx* ctx);
                                0: the point-wise kernels with global atomics */
 #define IBLBM_OPT_BAND_PASS 2 /* per-particle kernels only: 1 = u* at the band nodes (Eq. 5)
                                  in a lattice-ordered pass before the forcing passes
-                                 (default in 3-D), 0 = inside the first interpolation
-                                 pass (default in 2-D); the results are identical */
+                                 (default in 3-D, and in 2-D where the particles' LDS
+                                 boxes together cover at least half the lattice), 0 =
+                                 inside the first interpolation pass (the other 2-D
+                                 default); the results are identical */
 #define IBLBM_OPT_STATS_EVERY 3 /* replaces the configuration's stats_every (>= 0) */
 #define IBLBM_OPT_TIMING_EVERY 4 /* >= 1 (default 1): with timing on, only the launches of
                                     steps whose index is a multiple of the value carry

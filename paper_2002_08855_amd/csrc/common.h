@@ -166,6 +166,7 @@ struct iblbm_ctx {
   int npatch = 0;
   bool patched = false;       // some particle has more than one unit
   bool patch_ok = false;      // every unit fits one workgroup
+  double box_cover = 0.0;     // sum of the units' box nodes over the lattice nodes
   int *pt_owner = nullptr, *pt_m0 = nullptr, *pt_mc = nullptr;  // npatch
   double *pt_rlo = nullptr, *pt_rhi = nullptr;                  // npatch x 3 offset range
   std::vector<int> hpt_mc;    // host copy of pt_mc

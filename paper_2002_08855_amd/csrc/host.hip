@@ -193,6 +193,7 @@ void build_patches(iblbm_ctx* c) {
   std::vector<int> own, m0v, mcv;
   std::vector<double> rlo, rhi;
   long long cap = 1;
+  double box_total = 0.0;
   bool ok_all = true;
   c->full_side = 0;
   for (int p = 0; p < c->np; p++) {
@@ -212,8 +213,10 @@ void build_patches(iblbm_ctx* c) {
         rhi.push_back(u.hi[a]);
       }
       cap = std::max(cap, u.nodes);
+      box_total += (double)u.nodes;
     }
   }
+  c->box_cover = box_total / (double)c->N;
   int* ip[] = {c->pt_owner, c->pt_m0, c->pt_mc};
   for (int* q : ip)
     if (q) dfree(c, q);

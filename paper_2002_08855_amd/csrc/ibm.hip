@@ -1148,7 +1148,15 @@ bool ibm_uses_lds(const iblbm_ctx* c) {
 // u* of every node from a lattice-ordered pass after the collision (the default in 3-D,
 // where the band covers a large part of the lattice and overlapping particle boxes would
 // read shared nodes repeatedly), or at the touched nodes inside the first interpolation
-static bool band_pass(const iblbm_ctx* c) { return c->band_pass < 0 ? c->dim == 3 : c->band_pass != 0; }
+// Band u* in a lattice pass by default in 3-D, and in 2-D where the units' boxes cover at
+// least half the lattice: the first interpolation pass then reads more PDFs, over the
+// overlapping boxes, than one pass over every node does (2048^2 with 5340 disks of
+// diameter 20, coverage 0.80: measured 2.6% faster; 4096 disks of diameter 10, coverage
+// 0.22: 8% slower)
+static bool band_pass(const iblbm_ctx* c) {
+  if (c->band_pass >= 0) return c->band_pass != 0;
+  return c->dim == 3 || c->box_cover >= 0.5;
+}
 
 bool ibm_ustar_lattice(const iblbm_ctx* c) { return c->np > 0 && ibm_uses_lds(c) && band_pass(c); }
 

@@ -258,10 +258,15 @@ struct InteriorArgs {
 // row order (the A-A access of the step's parity).  The immersed-boundary passes of the
 // next step and the interior momentum of the particles read it instead of the PDFs.
 template <int DIM, class T, int PAR>
-__global__ __launch_bounds__(256) void k_ustar_all(InteriorArgs<typename Store<T>::C> a, int nbx) {
+__global__ __launch_bounds__(256) void k_ustar_all(InteriorArgs<typename Store<T>::C> a, int nbx,
+                                                   int xcd_per) {
   using C = typename Store<T>::C;
   using L = Lat<DIM>;
-  const int bx = blockIdx.x % nbx, row = blockIdx.x / nbx;
+  // XCD-aware order (xcd_per > 0), as in the collide-stream step: adjacent rows share an
+  // XCD and its L2
+  const int b = blockIdx.x;
+  const int lb = xcd_per > 0 ? (b & 7) * xcd_per + (b >> 3) : b;
+  const int bx = lb % nbx, row = lb / nbx;
   const int x = bx * 256 + threadIdx.x;
   if (x >= a.g.n[0]) return;
   const int y = row % a.g.n[1], z = row / a.g.n[1];
@@ -490,10 +495,15 @@ struct RunUstarAll {
     auto a = RunInterior<DIM, T>::args(c, nullptr, nullptr);
     int nbx = (c->cfg.n[0] + 255) / 256;
     unsigned nblk = (unsigned)((long long)nbx * c->cfg.n[1] * c->cfg.n[2]);
+    // XCD-aware order in 2-D only (measured slower at 256^3, where a row's z neighbours
+    // lie a whole plane of rows away)
+    int xcd_per = DIM == 2 && nblk % 8 == 0 ? (int)(nblk / 8) : 0;
     if (c->parity == 0)
-      hipLaunchKernelGGL((k_ustar_all<DIM, T, 0>), dim3(nblk), dim3(256), 0, c->stream, a, nbx);
+      hipLaunchKernelGGL((k_ustar_all<DIM, T, 0>), dim3(nblk), dim3(256), 0, c->stream, a, nbx,
+                         xcd_per);
     else
-      hipLaunchKernelGGL((k_ustar_all<DIM, T, 1>), dim3(nblk), dim3(256), 0, c->stream, a, nbx);
+      hipLaunchKernelGGL((k_ustar_all<DIM, T, 1>), dim3(nblk), dim3(256), 0, c->stream, a, nbx,
+                         xcd_per);
   }
 };
 
