@@ -42,7 +42,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(group, p, nmk, band_nodes):
+def algorithmic_bytes(group, p, nmk, band_nodes, band_lattice=True):
     """Bytes one launch of a kernel group must move (f_0, padding and the method's own
     bookkeeping not credited):
       collide-stream   2 (q-1) s per node + d cs per band node (the force read)
@@ -51,8 +51,9 @@ def algorithmic_bytes(group, p, nmk, band_nodes):
                        FP64, U_b and dF); split as interpolation d cs per band node +
                        12 d per point (u read; offsets, U_b) and spreading d cs per band
                        node + 4 d per point (f update; dF)
-    with s the stored PDF size and cs the compute size (4, and 8 in FP64).  In 2-D the band u* is made inside the first of the mdf_iters
-    interpolation launches, so each interpolation launch carries 1/mdf_iters of it."""
+    with s the stored PDF size and cs the compute size (4, and 8 in FP64).  Where the band
+    u* is made inside the first of the mdf_iters interpolation launches (band_lattice
+    false, a 2-D mode), each interpolation launch carries 1/mdf_iters of it."""
     dim = p["dim"]
     q = 9 if dim == 2 else 19
     s = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[p["storage"]]
@@ -65,7 +66,7 @@ def algorithmic_bytes(group, p, nmk, band_nodes):
         return band
     if group == "interp":
         b = dim * cs * band_nodes + nmk * 12 * dim
-        if dim == 2:
+        if not band_lattice:
             b += band / max(1, p["mdf_iters"])
         return b
     if group == "spread":
@@ -104,6 +105,7 @@ def run(args):
     per_group = {g: (st["time_ms"][g] / nb) for g in GROUPS if st["launches"][g]}
     dominant = max(per_group, key=per_group.get)
     band_nodes = st["band_nodes"]
+    band_lattice = bool(st["band_lattice"])
     # the collide-stream kernel by itself (events with its launch), over the same steps
     sim.set_timing(1 << GROUPS.index("collide"))
     sim.set_timing_kernel(True)
@@ -135,7 +137,7 @@ def run(args):
     mlups = N * args.steps / (1e6 * secs)
     launches = st2["launches"][dominant]
     avg_ms = st2["time_ms"][dominant] / max(1, launches)
-    nbytes = algorithmic_bytes(dominant, p, nmk, band_nodes)
+    nbytes = algorithmic_bytes(dominant, p, nmk, band_nodes, band_lattice)
     roof = None
     if nbytes is not None:
         ach = nbytes / (avg_ms * 1e-3) / 1e9
@@ -156,7 +158,7 @@ def run(args):
     # the collide-stream kernel against the HBM roofline
     roof_collide = None
     if st_c["launches"]["collide"]:
-        nb_c = algorithmic_bytes("collide", p, nmk, band_nodes)
+        nb_c = algorithmic_bytes("collide", p, nmk, band_nodes, band_lattice)
         ms_c = st_c["time_ms"]["collide"] / st_c["launches"]["collide"]
         ach_c = nb_c / (ms_c * 1e-3) / 1e9
         roof_collide = {"kernel": "k_collide_stream", "bound": "hbm", "achieved": round(ach_c, 1),

@@ -114,6 +114,9 @@ typedef struct {
   int64_t band_nodes;        /* nodes inside some point's support at the last step */
   double time_ms[IBLBM_NGROUPS];   /* accumulated kernel time per group (timing on) */
   int64_t launches[IBLBM_NGROUPS]; /* kernel launches per group (timing on) */
+  int32_t band_lattice;      /* 1: the band u* comes from the lattice u* pass, 0: from the
+                                first interpolation pass (IBLBM_OPT_BAND_PASS) */
+  int32_t reserved;          /* 0 */
 } iblbm_stats;
 
 /* Create a context: validate cfg (tau > 0.5, sizes, enums, struct_size), allocate the

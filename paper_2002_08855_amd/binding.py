@@ -46,6 +46,7 @@ class Stats(C.Structure):
         ("step", C.c_int64), ("slip_rms", C.c_double), ("truncated", C.c_int64),
         ("n_pairs", C.c_int64), ("flags", C.c_int32), ("fallbacks", C.c_int32),
         ("band_nodes", C.c_int64), ("time_ms", C.c_double * 8), ("launches", C.c_int64 * 8),
+        ("band_lattice", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -294,7 +295,8 @@ class Sim:
     def stats(self):
         s = Stats()
         self._check(lib().iblbm_get_stats(self.h, C.byref(s)))
-        d = {k: getattr(s, k) for k, _ in Stats._fields_ if k not in ("time_ms", "launches")}
+        d = {k: getattr(s, k) for k, _ in Stats._fields_
+             if k not in ("time_ms", "launches", "reserved")}
         d["time_ms"] = dict(zip(TIMERS, list(s.time_ms)))
         d["launches"] = dict(zip(TIMERS, list(s.launches)))
         return d

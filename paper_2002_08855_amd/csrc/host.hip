@@ -951,6 +951,7 @@ iblbm_status iblbm_get_stats(iblbm_ctx* c, iblbm_stats* o) {
   o->step = c->step;
   o->slip_rms = c->slip_rms;
   o->fallbacks = c->fallbacks;
+  o->band_lattice = ibm_ustar_lattice(c) ? 1 : 0;
   for (int g = 0; g < IBLBM_NGROUPS; g++) {
     o->time_ms[g] = c->time_ms[g];
     o->launches[g] = c->launches[g];

@@ -119,7 +119,8 @@ def _cfg1(name="cavity128_f64"):
 def test_cavity128_f64_particles_100_steps(name, lds, band):
     """The 2-D FP64 workload (16 disks): fields and particle states after 100 steps within
     1e-12 relative, with the per-particle LDS kernels (band u* inside the first
-    interpolation, the 2-D default, or in its own pass) and the point-wise ones; with
+    interpolation, the default for boxes covering 0.22 of the lattice, or in its own pass)
+    and the point-wise ones; with
     MDF-3 and the 4-point kernel, and with the single-pass thickened shell (3-point
     kernel, drs = 1.9)."""
     p, parts = _cfg1(name)
@@ -195,7 +196,7 @@ def test_pairs_cells_bit_exact(dim, n, count):
     assert np.array_equal(g.pairs(), o.pairs())
 
 
-@pytest.mark.parametrize("dim,n,count,band", [(2, (150, 130), 70, None), (2, (150, 130), 70, 1),
+@pytest.mark.parametrize("dim,n,count,band", [(2, (150, 130), 70, None), (2, (150, 130), 70, 0),
                                             (3, (56, 52, 48), 40, None), (3, (56, 52, 48), 40, 0)])
 def test_dense_shared_support_nodes_f64(dim, n, count, band):
     """Particles 0.05 to 1.3 lu apart, so that the delta-function supports of neighbours
@@ -217,6 +218,32 @@ def test_dense_shared_support_nodes_f64(dim, n, count, band):
     for k in ("X", "U", "F_h"):
         assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))
     assert np.array_equal(g.pairs(), o.pairs())
+
+
+@pytest.mark.parametrize("dim,n,count,D,lattice", [
+    (2, (128, 128), 16, 10.0, 0),   # boxes cover 0.22 of the lattice
+    (2, (64, 64), 9, 16.0, 1),      # boxes cover more than half
+    (3, (48, 44, 40), 8, 10.0, 1),  # 3-D: always the lattice pass
+])
+def test_band_mode_default_follows_box_coverage(dim, n, count, D, lattice):
+    """The default band u* mode: a lattice-ordered pass in 3-D and in 2-D where the
+    particles' LDS boxes cover at least half the lattice, else inside the first
+    interpolation pass; the option overrides it."""
+    b = _gpu()
+    side = int(round(count ** (1.0 / dim)))
+    pitch = min(n[:dim]) / side
+    X = inputs.jittered_grid(seed=3, nx=side, ny=side, pitch=pitch, origin=pitch / 2, jitter=0.5,
+                             **({"nz": side} if dim == 3 else {}))
+    box = sum(u[2] for u in b.plan_units(dim, "f64", D))
+    cover = len(X) * box / np.prod(n)
+    assert (cover >= 0.5) == bool(lattice) or dim == 3, cover
+    s = b.Sim(inputs.default_params(dim, n, tau=0.8, storage="f64"))
+    s.add_particles(X, np.full(len(X), D), np.full(len(X), 1.5))
+    s.step(1)
+    assert s.stats()["band_lattice"] == lattice
+    s.set_band_pass(not lattice)
+    s.step(1)
+    assert s.stats()["band_lattice"] == (not lattice)
 
 
 @pytest.mark.parametrize("lds,storage,tol,band,btdf", [
