@@ -26,7 +26,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores, published
 # odd, so the timed launches fall on both parities of the A-A streaming
 TIMING_EVERY = 5
 GROUPS = ["collide", "band", "interp", "spread", "interior", "particle", "mlp", "other"]
-KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_ustar_all + k_mark_lds",
+KERNEL_NAME = {"collide": "k_collide_stream", "band": "k_ustar_all",
                "interp": "k_interp_lds", "spread": "k_spread_lds",
                "interior": "k_interior", "particle": "k_cells + k_pairs + k_loads_newton",
                "mlp": "k_features + k_mlp_infer"}

@@ -95,8 +95,8 @@ typedef struct {
 /* kernel groups timed when timing is on (iblbm_set_timing) */
 typedef enum {
   IBLBM_T_COLLIDE = 0,  /* fused collide + force + A-A stream */
-  IBLBM_T_BAND = 1,     /* band marking and band u* */
-  IBLBM_T_INTERP = 2,   /* IBM interpolation + point force */
+  IBLBM_T_BAND = 1,     /* band u* (the lattice u* pass) */
+  IBLBM_T_INTERP = 2,   /* IBM interpolation + point force; the first pass also marks the band */
   IBLBM_T_SPREAD = 3,   /* IBM spreading */
   IBLBM_T_INTERIOR = 4, /* fluid momentum inside particles */
   IBLBM_T_PARTICLE = 5, /* cells, pairs, loads, Newton-Euler */

@@ -140,7 +140,9 @@ struct iblbm_ctx {
   bool ibm_lds = true; // per-particle LDS kernels for interpolation and spreading
   int band_pass = -1;   // band u* in its own pass (1) or in the first interpolation (0);
                         // -1: by dimension
-  bool band_pending = false;  // the next interpolation pass builds the band
+  // the next interpolation pass builds the band: 0 no, 1 with u* from the PDFs at the
+  // band, 2 with u* from the lattice u* pass
+  int band_pending = 0;
   bool ustar_valid = false;   // ustar holds u* of every node for the current PDFs
   // markers
   int nmk = 0, capm = 0;
@@ -204,7 +206,7 @@ struct iblbm_ctx {
   // one captured step per (PDF parity, band-bitmap buffer), and the host-side flags the
   // captured step left behind
   hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool gend_band_pending[4] = {false, false, false, false};
+  int gend_band_pending[4] = {0, 0, 0, 0};
   bool gend_ustar_valid[4] = {false, false, false, false};
   bool graph_dirty = true;
   bool capturing = false;  // enqueue_step is being recorded into a graph

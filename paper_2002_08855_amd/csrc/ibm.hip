@@ -424,54 +424,14 @@ __device__ __forceinline__ void band_rows(const MarkerGeo& g, const PBox<DIM>& b
   }
 }
 
-// Band of this step for the per-particle path: flag the support nodes of every point of
-// the particle in LDS, list them in ascending order for the forcing passes of the step,
-// clear the force there, and set them in the band bitmap with one atomic per (row,
-// 32-node word) of the particle's box.  u* comes from the lattice pass after the
-// previous collision.
-template <int DIM, class C>
-__global__ __launch_bounds__(LDS_THREADS) void k_mark_lds(LdsArgs<C> a) {
-  extern __shared__ double smem_d[];
-  if (a.cond && *a.cond == 0) return;
-  // tested with the box below, so that its load overlaps the particle's
-  const bool stop = halted(a.P.status);
-  int* wcnt = reinterpret_cast<int*>(smem_d);
-  uint8_t* flag = reinterpret_cast<uint8_t*>(wcnt + 20);
-  const int q = blockIdx.x;
-  int p, m0, mc;
-  PBox<DIM> b;
-  unit_of<DIM>(a, q, p, m0, mc, b);
-  if (stop || b.n > a.cap) return;  // the host sizes cap for the largest unit
-  for (int t = threadIdx.x; t < (b.n + 3) / 4; t += blockDim.x) reinterpret_cast<uint32_t*>(flag)[t] = 0u;
-  __syncthreads();
-  for (int k = m0 + threadIdx.x; k < m0 + mc; k += blockDim.x) {
-    double X[3], Ub[3];
-    marker_pos_vel(a.P, k, X, Ub, DIM);
-    PointWeights<C> pw;
-    point_weights<DIM, C>(a.g.kind, X, pw);
-    visit_support<DIM, C>(a.g, b, pw, [&](int loc, C) { flag[loc] = 1; });
-  }
-  __syncthreads();
-  uint16_t* tl = a.tlist + (size_t)q * a.cap;
-  const int ntouch = list_flags(flag, b.n, tl, wcnt);
-  if (threadIdx.x == 0) a.tcount[q] = ntouch;
-  for (int j = threadIdx.x; j < ntouch; j += blockDim.x) {
-    const int t = tl[j];
-    int x, y, z;
-    b.at(t, x, y, z);
-    const C zero[3] = {C(0), C(0), C(0)};
-    store_node<DIM>(a.facc, (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd, zero);
-  }
-  band_rows<DIM>(a.g, b, flag, a.bmap, a.nwx);
-}
-
 // Interpolation (+ point force) for one forcing pass through the particle's LDS box.
 // The touched nodes of the step are listed in ascending order (so that neighbouring
 // lanes stage neighbouring nodes), staged into LDS as u = u* + f/(2 rho0) (Eq. 7), and
-// gathered by one lane per point.  The list, u* and the cleared force come from the
-// marking kernel and the lattice u* pass, or, with FIRST, are made here: the nodes are
-// flagged (one lane per point) and listed by ballot compaction, u* comes from their PDFs,
-// and they enter the band bitmap.
+// gathered by one lane per point.  Later passes (FIRST = 0) take the list from the step's
+// first pass, u* from the lattice u* array.  The first pass (FIRST = 1, 2) makes the band:
+// the nodes are flagged (one lane per point), listed by ballot compaction and kept for
+// the later passes, their force is cleared, and they enter the band bitmap; u* comes from
+// their PDFs (FIRST = 1) or from the lattice u* array (FIRST = 2).
 template <int DIM, class T, int PAR, int FIRST>
 __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Store<T>::C> a) {
   using C = typename Store<T>::C;
@@ -530,8 +490,33 @@ __global__ __launch_bounds__(LDS_THREADS) void k_interp_lds(LdsArgs<typename Sto
     nodes = tl;
   }
   T* slot[L::Q - 1];
-  if (FIRST) slots_of<DIM, T>(a.slot, slot);
-  if (FIRST) {
+  if (FIRST == 1) slots_of<DIM, T>(a.slot, slot);
+  if (FIRST == 2) {
+    // u* of the listed nodes from the lattice u* array; their force starts at zero
+    for (int j0 = threadIdx.x; j0 < ntouch; j0 += LIST_BATCH * blockDim.x) {
+      int t[LIST_BATCH];
+      size_t ii[LIST_BATCH];
+      typename NodeVec<C, DIM>::T us[LIST_BATCH];
+#pragma unroll
+      for (int u = 0; u < LIST_BATCH; u++) {
+        const int j = j0 + u * (int)blockDim.x;
+        t[u] = j < ntouch ? (int)nodes[j] : -1;
+        if (t[u] < 0) continue;
+        int x, y, z;
+        b.at(t[u], x, y, z);
+        ii[u] = (size_t)(x + a.g.n[0] * (y + a.g.n[1] * z)) * a.vd;
+        us[u] = load_node<DIM>(a.ustar, ii[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < LIST_BATCH; u++) {
+        if (t[u] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < DIM; c++) ub[c * a.cap + t[u]] = comp<C>(us[u], c);
+        const C zero[3] = {C(0), C(0), C(0)};
+        store_node<DIM>(a.facc, ii[u], zero);
+      }
+    }
+  } else if (FIRST == 1) {
     // u* from the PDFs at the listed nodes (Eqs. 4-5); the force there starts at zero.
     // FIRST_BATCH nodes per lane at a time, their PDF loads issued before any is used, so
     // that the loads of several nodes share one memory latency
@@ -721,7 +706,7 @@ __global__ __launch_bounds__(LDS_THREADS) void k_spread_lds(LdsArgs<C> a) {
       mag = fmax(mag, fabs(double(F[c])));
     }
   }
-  // the touched nodes of the step (listed by the marking kernel or the first pass),
+  // the touched nodes of the step (listed by the step's first interpolation pass),
   // copied into LDS after the point loads above are issued, so that the latencies overlap
   uint16_t* tl = reinterpret_cast<uint16_t*>(red + 16);
   const uint16_t* gl = a.tlist + (size_t)q * a.cap;
@@ -1022,6 +1007,7 @@ struct RunInterp {
     raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 0>, dyn);
     raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 1>, dyn);
     raise_lds_limit((const void*)k_interp_lds<DIM, T, 1, 1>, dyn);
+    raise_lds_limit((const void*)k_interp_lds<DIM, T, 0, 2>, dyn);
   }
   static void run(iblbm_ctx* c, int first, int mode, bool* done) {
     using C = typename Store<T>::C;
@@ -1029,12 +1015,14 @@ struct RunInterp {
     size_t bytes = lds_bytes(c, sizeof(C), true);
     if (!ibm_uses_lds(c)) return;
     auto a = make_lds_args<T>(c, first, mode);
-    if (c->band_pending) {
+    if (c->band_pending == 2) {
+      go<0, 2>(c, a, bytes);
+    } else if (c->band_pending == 1) {
       if (c->parity == 0) go<0, 1>(c, a, bytes); else go<1, 1>(c, a, bytes);
     } else {
       go<0, 0>(c, a, bytes);
     }
-    c->band_pending = false;
+    c->band_pending = 0;
     *done = true;
   }
   template <int PAR, int FIRST>
@@ -1053,17 +1041,6 @@ struct RunInterp {
     if (a.mode == 1 || a.mode == 3)
       hipLaunchKernelGGL(k_sum_units, dim3(1), dim3(256), 0, c->stream, c->slip_part, c->npatch,
                          c->dstats);
-  }
-};
-
-// band of the per-particle path with the lattice-ordered u*: bitmap and cleared force
-template <int DIM, class T>
-struct RunMarkLds {
-  static void run(iblbm_ctx* c) {
-    using C = typename Store<T>::C;
-    auto a = make_lds_args<T>(c, 0, 0);
-    size_t bytes = 20 * sizeof(int) + (((size_t)c->box_cap + 3) & ~(size_t)3);
-    hipLaunchKernelGGL((k_mark_lds<DIM, C>), dim3(c->npatch), dim3(lds_threads(c)), bytes, c->stream, a);
   }
 };
 
@@ -1161,14 +1138,15 @@ static bool band_pass(const iblbm_ctx* c) {
 bool ibm_ustar_lattice(const iblbm_ctx* c) { return c->np > 0 && ibm_uses_lds(c) && band_pass(c); }
 
 void ibm_band(iblbm_ctx* c) {
-  c->band_pending = false;
+  c->band_pending = 0;
   if (c->np == 0) return;
   if (ibm_uses_lds(c)) {
+    // the first interpolation pass marks the band
     if (band_pass(c)) {
       if (!c->ustar_valid) lbm_ustar_all(c);
-      dispatch<RunMarkLds>(c);
+      c->band_pending = 2;
     } else {
-      c->band_pending = true;
+      c->band_pending = 1;
     }
     return;
   }
@@ -1205,10 +1183,8 @@ void ibm_prepare_launches(iblbm_ctx* c) { dispatch<RunLdsLimits>(c); }
 void ibm_band_redo(iblbm_ctx* c) {
   if (c->np == 0) return;
   if (ibm_uses_lds(c)) {
-    if (band_pass(c))
-      dispatch<RunMarkLds>(c);  // clears the force again; u* is unchanged
-    else
-      c->band_pending = true;
+    // the next first pass marks the band again and clears its force; u* is unchanged
+    c->band_pending = band_pass(c) ? 2 : 1;
   } else {
     dispatch<RunBandPrep>(c);
   }

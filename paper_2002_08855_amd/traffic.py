@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
 SOURCE_OF = {"k_collide_stream": "lbm.hip", "k_interior": "lbm.hip", "k_interp_lds": "ibm.hip",
              "k_spread_lds": "ibm.hip", "k_band_prep": "ibm.hip", "k_ustar_all": "lbm.hip",
-             "k_mark_lds": "ibm.hip", "k_pairs": "particles.hip",
+             "k_pairs": "particles.hip",
              "k_cells": "particles.hip", "k_loads_newton": "particles.hip",
              "k_features": "mlp.hip", "k_mlp_infer": "mlp.hip"}
 
