@@ -341,11 +341,12 @@ def test_large_sphere(lds):
     assert rel_l2(g.particles()["U"], o.particles()["U"]) < 1e-11
 
 
-@pytest.mark.parametrize("band", [None, 1])
+@pytest.mark.parametrize("band", [0, 1])
 def test_disks_with_more_points_than_a_workgroup(band):
     """Disks with 2000 points (more than one workgroup's 1024 lanes) next to a small one:
     the large disks are split into runs of points, the small one stays whole; FP64
-    parity over both step parities."""
+    parity over both step parities, with the band u* made in the first interpolation pass
+    and in the lattice u* pass."""
     p = inputs.default_params(2, (120, 100), tau=0.8, storage="f64", mdf_iters=3)
     g, o = _pair(p)
     if band is not None:
@@ -362,12 +363,13 @@ def test_disks_with_more_points_than_a_workgroup(band):
         assert rel_l2(pg[k], po[k]) < 1e-11, (k, rel_l2(pg[k], po[k]))
 
 
-@pytest.mark.parametrize("band", [None, 1])
+@pytest.mark.parametrize("band", [0, 1])
 def test_wide_disk_box_rows_span_four_bitmap_words(band):
     """A disk of D = 64 whose LDS box starts at x = 31 (one node before a 32-node word
     boundary): each 69-node box row spans four words of the band bitmap, and the force of
     every flagged node must reach the collision.  FP64 parity after 12 steps, with the band
-    made in the first interpolation pass (2-D default) and in its own pass."""
+    u* made in the first interpolation pass and in the lattice u* pass (the first pass
+    marks the band in both)."""
     p = inputs.default_params(2, (128, 112), tau=0.8, storage="f64", mdf_iters=2)
     g, o = _pair(p)
     if band is not None:
