@@ -139,7 +139,7 @@ struct iblbm_ctx {
   int lds_max = 65536; // LDS bytes a workgroup may use on this device
   bool ibm_lds = true; // per-particle LDS kernels for interpolation and spreading
   int band_pass = -1;   // band u* in its own pass (1) or in the first interpolation (0);
-                        // -1: by dimension
+                        // -1: by dimension and box coverage (box_cover)
   // the next interpolation pass builds the band: 0 no, 1 with u* from the PDFs at the
   // band, 2 with u* from the lattice u* pass
   int band_pending = 0;

@@ -1120,16 +1120,13 @@ bool ibm_uses_lds(const iblbm_ctx* c) {
          lds_bytes(c, cs, false) <= (size_t)c->lds_max;
 }
 
-// Band of this step.  On the per-particle path the first interpolation pass builds it;
-// otherwise list the touched segments and compute u* there now.
-// u* of every node from a lattice-ordered pass after the collision (the default in 3-D,
-// where the band covers a large part of the lattice and overlapping particle boxes would
-// read shared nodes repeatedly), or at the touched nodes inside the first interpolation
-// Band u* in a lattice pass by default in 3-D, and in 2-D where the units' boxes cover at
-// least half the lattice: the first interpolation pass then reads more PDFs, over the
-// overlapping boxes, than one pass over every node does (2048^2 with 5340 disks of
-// diameter 20, coverage 0.80: measured 2.6% faster; 4096 disks of diameter 10, coverage
-// 0.22: 8% slower)
+// Band u*: from a lattice-ordered pass over every node after the collision, or at the
+// touched nodes inside the first interpolation pass.  The lattice pass is the default in
+// 3-D, where the band covers a large part of the lattice and overlapping particle boxes
+// would read shared nodes repeatedly, and in 2-D where the units' boxes cover at least
+// half the lattice, so that the first pass would read more PDFs than one pass over every
+// node (2048^2 with 5340 disks of diameter 20, coverage 0.80: measured 2.6% faster; 4096
+// disks of diameter 10, coverage 0.22: 8% slower).
 static bool band_pass(const iblbm_ctx* c) {
   if (c->band_pass >= 0) return c->band_pass != 0;
   return c->dim == 3 || c->box_cover >= 0.5;
@@ -1137,6 +1134,8 @@ static bool band_pass(const iblbm_ctx* c) {
 
 bool ibm_ustar_lattice(const iblbm_ctx* c) { return c->np > 0 && ibm_uses_lds(c) && band_pass(c); }
 
+// Band of this step.  On the per-particle path the first interpolation pass builds it;
+// otherwise list the touched segments and compute u* there now.
 void ibm_band(iblbm_ctx* c) {
   c->band_pending = 0;
   if (c->np == 0) return;
